@@ -1,0 +1,260 @@
+/*
+ * nmodes -- seismic normal modes of layered, rotating planets on AMD MI355X.
+ *
+ * C ABI of the GPU library.  It computes the eigenpairs of the mixed
+ * continuous-Galerkin elastic-gravitational pencil of
+ *   Shi, Li, Xi, Saad, de Hoop, "A non-perturbative approach to computing
+ *   seismic normal modes in rotating planets" (arXiv 1906.11082),
+ * in the Cowling approximation (Sec. 6.2, eq. "cowling"):
+ *
+ *     (A_G - E_G A_p^{-1} E_G^T) u = omega^2 M u,           (Omega = 0)
+ *     omega^2 M u - 2 i omega R u - A u = 0                  (Sec. 7, eq. "simplequad")
+ *
+ * with the matrices of the table of implicit matrix definitions (Sec. 4.2)
+ * built by the element formulas of Appendix A, on unstructured tetrahedral
+ * meshes with solid and fluid regions.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - Status: 0 success, NM_PARTIAL (1) a solve returned fewer converged pairs
+ *   than requested, negative values are errors (NM_E*).  nm_last_error()
+ *   returns a message for the last failing call on the calling thread.
+ * - Host arrays passed in are borrowed for the duration of the call only.
+ * - Device arrays are plain device pointers (hipMalloc'd or from any
+ *   allocator in the same process), row-major [rows][ncols] with the ncols
+ *   columns of a row contiguous.  A displacement block therefore is
+ *   [N][3][ncols]: node-major, components x,y,z, then columns.
+ * - "stream" is a hipStream_t (NULL = the default stream).  Calls that
+ *   return host data synchronise that stream before returning.
+ * - Displacement DOF numbering (the numbering is part of the result and is
+ *   bit-exact reproducible): geometric nodes are the vertices in input order,
+ *   then (degree 2) one node per edge, edges ordered by (min vertex, max
+ *   vertex).  A node carries a solid copy if it belongs to a solid
+ *   tetrahedron and a fluid copy if it belongs to a fluid one; the elements
+ *   are non-conforming across fluid-solid boundaries (Sec. 4.1).  All solid
+ *   copies come first, by geometric id, then all fluid copies.  DOF =
+ *   3*node + component.  Pressure DOFs: geometric nodes of the pressure
+ *   degree that belong to a fluid tetrahedron, by geometric id.
+ * - Element-local node order (for per-element-node inputs): vertices 0..3
+ *   of tet[k], then edge midpoints of edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+ */
+#ifndef NMODES_H
+#define NMODES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nm_status;
+enum {
+  NM_OK = 0,
+  NM_PARTIAL = 1,     /* solve finished with fewer converged pairs than asked */
+  NM_EINVAL = -1,     /* invalid argument (sizes, window, options) */
+  NM_EBADMESH = -2,   /* index out of range or tetrahedron with J <= 0 */
+  NM_ENOMEM = -3,     /* device or host allocation failed */
+  NM_EDEVICE = -4,    /* HIP / rocBLAS / rocSOLVER call failed */
+  NM_ENOCONV = -5     /* filter blow-up or Lanczos breakdown not recovered */
+};
+
+/* Matrices held by a pencil (nm_pencil_export_csr, nm_pencil_apply). */
+enum {
+  NM_MAT_AG = 0,   /* A_G: solid stiffness with gravity (n x n); the fluid block
+                      A_f is zero (buoyancy N^2 = 0, no fluid-fluid interface) */
+  NM_MAT_M = 1,    /* M = M_s (x) I_3, mass (n x n) */
+  NM_MAT_R = 2,    /* R = M_s (x) [Omega]_x, Coriolis int rho v.(Omega x u) (n x n) */
+  NM_MAT_KP = 3,   /* K_p = -A_p = int kappa^{-1} v^p p, SPD (n_p x n_p) */
+  NM_MAT_EG = 4    /* E_G = [E_FS; A_dg] (n x n_p) */
+};
+
+/* Operators of nm_pencil_apply (Y = op(X)). */
+enum {
+  NM_OP_AG = 0,     /* Y = A_G X                               X:[n][c]   Y:[n][c]   */
+  NM_OP_M = 1,      /* Y = M X                                 [n][c] -> [n][c]       */
+  NM_OP_R = 2,      /* Y = R X                                 [n][c] -> [n][c]       */
+  NM_OP_KP = 3,     /* Y = K_p X                               [n_p][c] -> [n_p][c]   */
+  NM_OP_EG = 4,     /* Y = E_G X                               [n_p][c] -> [n][c]     */
+  NM_OP_EGT = 5,    /* Y = E_G^T X                             [n][c] -> [n_p][c]     */
+  NM_OP_KPINV = 6,  /* Y = S_p(X), fixed-k Chebyshev-Jacobi solve with K_p          */
+  NM_OP_A = 7,      /* Y = (A_G + E_G S_p E_G^T) X, the Cowling operator            */
+  NM_OP_MINV = 8,   /* Y = S_M(X), fixed-k Chebyshev-Jacobi solve with M            */
+  NM_OP_B = 9       /* Y = S_M(A X)                                                 */
+};
+
+typedef struct nm_pencil nm_pencil;
+
+typedef struct {
+  int64_t n_vert;          /* V */
+  int64_t n_tet;           /* T */
+  const double* xyz;       /* host [V][3] */
+  const int32_t* tet;      /* host [T][4], vertex ids, positive orientation */
+  const int8_t* region;    /* host [T], 0 solid, 1 fluid */
+  int32_t disp_order;      /* 1 or 2 */
+  int32_t pres_order;      /* 1 or 2, <= disp_order */
+} nm_mesh;
+
+typedef struct {
+  const double* rho;          /* host [T] density */
+  const double* lam;          /* host [T] Lame lambda (fluid: kappa) */
+  const double* mu;           /* host [T] shear modulus (0 in fluid) */
+  const double* gprime;       /* host [T][Np][3] g' at element nodes, or NULL (no gravity) */
+  const double* grad_gprime;  /* host [T][Np][3][3], [i][j] = d_i g'_j, or NULL */
+  int32_t gprime_np;          /* Np of the two arrays above (4 or 10) */
+} nm_material;
+
+typedef struct {
+  int64_t n_geom;     /* geometric nodes (vertices + edges) */
+  int64_t n_node;     /* displacement nodes N (solid copies + fluid copies) */
+  int64_t n_solid;    /* solid copies */
+  int64_t n_disp;     /* n = 3 N */
+  int64_t n_pres;     /* pressure DOFs n_p */
+  int64_t nnzb;       /* blocks of the node graph (= nnz of M_s) */
+  int64_t nnz_kp;     /* nnz of K_p */
+  int64_t nnzb_eg;    /* (node, pressure) pairs of E_G */
+  int64_t n_fs_faces; /* fluid-solid faces */
+  double minv_lo, minv_hi;  /* element bounds of spec(D^{-1} M) */
+  double kp_lo, kp_hi;      /* element bounds of spec(D^{-1} K_p) */
+} nm_pencil_info;
+
+typedef struct {
+  int32_t kM;          /* Chebyshev-Jacobi steps of the M solve (0 = from minv_tol) */
+  int32_t kP;          /* steps of the K_p solve (0 = from kp_tol) */
+  double minv_tol;     /* bound 2 r^k of the M solve (0 = 1e-12) */
+  double kp_tol;       /* bound of the K_p solve (0 = 1e-13) */
+  int32_t precision;   /* 0 FP64, 1 FP32 values, vectors and accumulation */
+} nm_apply_opts;
+
+typedef struct {
+  int32_t degree;      /* filter degree, 0 = chosen from the spectrum bounds */
+  int32_t block;       /* block width b, 0 = auto */
+  int32_t precision;   /* 0 FP64 filter; 1 FP32 filter + FP64 Lanczos/RR/residual */
+  int32_t max_basis;   /* cap of the Krylov basis size, 0 = auto */
+  int32_t null_filter; /* lower side of the filter: -1 auto (no damping below a when the
+                          pencil has fluid, else damping), 0 damping below a, 1 factor
+                          lambda/b, 2 no damping below a */
+  int32_t verbose;     /* 0 quiet, 1 per-block log on stderr */
+  double minv_tol;     /* M-solve bound inside the filter (0 = 1e-10 FP64, 1e-7 FP32) */
+  double kp_tol;       /* K_p-solve bound (0 = 1e-13 FP64, 1e-7 FP32) */
+  double lmin, lmax;   /* spectrum bounds of M^{-1}A; lmax <= lmin: estimate */
+  double guard;        /* transition width beyond b as a fraction of b (0 = 1.0) */
+  uint64_t seed;       /* start block seed */
+  void* stream;        /* hipStream_t */
+} nm_eig_opts;
+
+typedef struct {
+  int32_t count;        /* pairs returned, lambda ascending */
+  int64_t n;            /* rows of X */
+  double* lambda;       /* host [count] omega^2 */
+  double* resid;        /* host [count] ||A x - l M x|| / (|l| ||M x||) */
+  double* X;            /* device [n][count], M-orthonormal, largest entry of each column > 0 */
+  int32_t degree;       /* filter degree used */
+  int32_t kM, kP;       /* inner solve steps used */
+  int32_t block;        /* block width used */
+  int32_t basis;        /* final Krylov basis size */
+  int64_t bapps;        /* column applications of B = M^{-1} A */
+  double lmin, lmax;    /* spectrum bounds used */
+  double seconds;       /* wall time of the solve */
+  double bytes;         /* algorithmic HBM bytes of all filter applications */
+  double filter_seconds;/* time inside filter applications */
+  /* hot kernel (a middle Chebyshev-Jacobi step of the M solve inside the
+     filter): launches, sampled launches timed with HIP events on the solve's
+     stream, their mean duration, and its algorithmic bytes per launch */
+  int64_t hot_launches, hot_samples;
+  double hot_ms, hot_bytes;
+} nm_eig_result;
+
+typedef struct {
+  int32_t count;        /* rotating modes with omega > 0, omega^2 in [a, b] */
+  int64_t n;
+  double* omega;        /* host [count] ascending */
+  double* U;            /* device [n][count][2] complex (re, im) modes, normalised by
+                           u^H M u - (i/omega) u^H R u = 1, largest entry real > 0 */
+  double seconds;
+} nm_rot_result;
+
+/* Build the pencil: numbering, CSR patterns and all matrix values on the
+ * device (Sec. 4.2 table, Appendix A).  omega: rotation vector (may be
+ * NULL = 0).  Fails with NM_EBADMESH naming the first tetrahedron with
+ * J <= 0 or an index out of range. */
+nm_status nm_assemble(const nm_mesh* mesh, const nm_material* mat, const double omega[3],
+                      void* stream, nm_pencil** out);
+
+nm_status nm_pencil_info_get(const nm_pencil* p, nm_pencil_info* info);
+
+/* Two-call CSR export of one matrix (NM_MAT_*) into caller host buffers:
+ * with row_ptr == NULL only *nrows, *ncols, *nnz are filled; then call again
+ * with row_ptr [nrows+1], col [nnz], val [nnz] (val may be NULL).
+ * Columns of a row strictly increase; the vector matrices are exported with
+ * full 3x3 blocks (zeros stored). */
+nm_status nm_pencil_export_csr(const nm_pencil* p, int32_t which, int64_t* nrows, int64_t* ncols,
+                               int64_t* nnz, int64_t* row_ptr, int32_t* col, double* val);
+
+/* Geometric node of each displacement node (host [N]) and of each pressure
+ * DOF (host [n_p]); either may be NULL. */
+nm_status nm_pencil_nodes(const nm_pencil* p, int64_t* node_geom, int64_t* pres_geom);
+
+/* Y = op(X) on the device (NM_OP_*), X and Y device arrays as above, X != Y.
+ * opts may be NULL (FP64, default tolerances).  With precision 1 the
+ * arrays are float. */
+nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const void* X, void* Y,
+                          const nm_apply_opts* opts, void* stream);
+
+/* Jackson-damped Chebyshev coefficients mu[0..m] of the indicator of [a, b]
+ * after mapping [lmin, lmax] onto [-1, 1] (the polynomial filter). */
+nm_status nm_filter_coeffs(double a, double b, double lmin, double lmax, int32_t m, double* mu);
+
+/* Filter degree chosen by the library: the smallest degree whose filter
+ * stays below 1 % of its window-edge level beyond b (1 + guard) (guard <= 0:
+ * 1.0).  mode 0: no requirement below a (the spectrum below the window is
+ * an exactly degenerate null space); mode 1: the same bound below
+ * a - guard (a - lmin); mode 2: the filter carries the factor lambda / b. */
+nm_status nm_filter_degree(double a, double b, double lmin, double lmax, double guard, int32_t mode,
+                           int32_t* m);
+
+/* Y = p(B) X (null_scale == 0) or Y = ((B - null_shift)/null_scale) p(B) X,
+ * p(t) = sum_k mu_k T_k((t - c)/e), B = S_M A: one polynomial-filter
+ * application (Sec. 6.1, polynomial filtering), device arrays [n][ncols]. */
+nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, double c, double e,
+                          double null_shift, double null_scale, int32_t ncols, const void* X,
+                          void* Y, const nm_apply_opts* opts, void* stream);
+
+/* Bounds [lmin, lmax] enclosing the spectrum of M^{-1} A (the
+ * interval the Chebyshev filter is defined on), from `steps` Lanczos steps
+ * in the M-inner product with the random start vector of `seed`. */
+nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, void* stream, double* lmin,
+                             double* lmax);
+
+/* Eigenpairs of the Cowling pencil with a <= omega^2 <= b: the min(nev,
+ * count) smallest, by polynomial-filtered block Lanczos in the M-inner
+ * product with Rayleigh-Ritz on (A, M) (Sec. 6.1).  tol bounds the
+ * residual of every returned pair. */
+nm_status nm_filtered_eig(const nm_pencil* p, double a, double b, int32_t nev, double tol,
+                          const nm_eig_opts* opts, nm_eig_result** out);
+
+/* Rotating modes by projection on the non-rotating eigenvectors of basis
+ * (Sec. 7, eqs. "linearpb", "sublinear0"): keeps omega > 0 with omega^2 in
+ * [a, b].  Uses the pencil's Omega. */
+nm_status nm_project_rotation(const nm_pencil* p, const nm_eig_result* basis, double a, double b,
+                              void* stream, nm_rot_result** out);
+
+/* Copy the eigenvectors of a result into dst (device if dst_is_device,
+ * else host), row-major [n][count] (rotation: [n][count][2]). */
+nm_status nm_result_copy_vectors(const nm_eig_result* r, void* dst, int32_t dst_is_device);
+nm_status nm_rot_copy_vectors(const nm_rot_result* r, void* dst, int32_t dst_is_device);
+
+void nm_result_free(nm_eig_result* r);
+void nm_rot_result_free(nm_rot_result* r);
+void nm_pencil_free(nm_pencil* p);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* nm_last_error(void);
+
+/* Library version string. */
+const char* nm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMODES_H */

@@ -1,0 +1,302 @@
+"""Python binding of libnmodes (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library (include/nmodes.h).  torch is
+imported first so that the library binds to the HIP runtime torch loaded;
+device arrays are torch tensors on the current device and the library runs
+on torch's current stream.  If the library is not built the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:
+    import torch
+except ImportError:  # pragma: no cover - the GPU path needs torch
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmodes.so")
+
+NM_OK, NM_PARTIAL = 0, 1
+MAT_AG, MAT_M, MAT_R, MAT_KP, MAT_EG = range(5)
+OP_AG, OP_M, OP_R, OP_KP, OP_EG, OP_EGT, OP_KPINV, OP_A, OP_MINV, OP_B = range(10)
+
+EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pencil_nodes", "nm_pencil_apply",
+            "nm_filter_coeffs", "nm_filter_degree", "nm_filter_apply", "nm_spectrum_bounds", "nm_filtered_eig", "nm_project_rotation",
+            "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
+            "nm_pencil_free", "nm_last_error", "nm_version"]
+
+
+class NMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("nmodes status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("n_vert", C.c_int64), ("n_tet", C.c_int64), ("xyz", C.c_void_p), ("tet", C.c_void_p),
+                ("region", C.c_void_p), ("disp_order", C.c_int32), ("pres_order", C.c_int32)]
+
+
+class _Material(C.Structure):
+    _fields_ = [("rho", C.c_void_p), ("lam", C.c_void_p), ("mu", C.c_void_p), ("gprime", C.c_void_p),
+                ("grad_gprime", C.c_void_p), ("gprime_np", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_geom", C.c_int64), ("n_node", C.c_int64), ("n_solid", C.c_int64), ("n_disp", C.c_int64),
+                ("n_pres", C.c_int64), ("nnzb", C.c_int64), ("nnz_kp", C.c_int64), ("nnzb_eg", C.c_int64),
+                ("n_fs_faces", C.c_int64), ("minv_lo", C.c_double), ("minv_hi", C.c_double),
+                ("kp_lo", C.c_double), ("kp_hi", C.c_double)]
+
+
+class _ApplyOpts(C.Structure):
+    _fields_ = [("kM", C.c_int32), ("kP", C.c_int32), ("minv_tol", C.c_double), ("kp_tol", C.c_double),
+                ("precision", C.c_int32)]
+
+
+class _EigOpts(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("block", C.c_int32), ("precision", C.c_int32), ("max_basis", C.c_int32),
+                ("null_filter", C.c_int32), ("verbose", C.c_int32), ("minv_tol", C.c_double),
+                ("kp_tol", C.c_double), ("lmin", C.c_double), ("lmax", C.c_double), ("guard", C.c_double),
+                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class _EigResult(C.Structure):
+    _fields_ = [("count", C.c_int32), ("n", C.c_int64), ("lam", C.POINTER(C.c_double)),
+                ("resid", C.POINTER(C.c_double)), ("X", C.c_void_p), ("degree", C.c_int32), ("kM", C.c_int32),
+                ("kP", C.c_int32), ("block", C.c_int32), ("basis", C.c_int32), ("bapps", C.c_int64),
+                ("lmin", C.c_double), ("lmax", C.c_double), ("seconds", C.c_double), ("bytes", C.c_double),
+                ("filter_seconds", C.c_double), ("hot_launches", C.c_int64), ("hot_samples", C.c_int64),
+                ("hot_ms", C.c_double), ("hot_bytes", C.c_double)]
+
+
+class _RotResult(C.Structure):
+    _fields_ = [("count", C.c_int32), ("n", C.c_int64), ("omega", C.POINTER(C.c_double)), ("U", C.c_void_p),
+                ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library(path: str | None = None):
+    """Load libnmodes.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError("libnmodes.so is not built: run paper_1906_11082_amd.build.build()")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    sig = {
+        "nm_assemble": ([C.POINTER(_Mesh), C.POINTER(_Material), P, P, C.POINTER(P)], C.c_int32),
+        "nm_pencil_info_get": ([P, C.POINTER(_Info)], C.c_int32),
+        "nm_pencil_export_csr": ([P, C.c_int32] + [C.POINTER(C.c_int64)] * 3 + [P, P, P], C.c_int32),
+        "nm_pencil_nodes": ([P, P, P], C.c_int32),
+        "nm_pencil_apply": ([P, C.c_int32, C.c_int32, P, P, C.POINTER(_ApplyOpts), P], C.c_int32),
+        "nm_filter_coeffs": ([C.c_double] * 4 + [C.c_int32, P], C.c_int32),
+        "nm_filter_degree": ([C.c_double] * 5 + [C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
+        "nm_filter_apply": ([P, P, C.c_int32] + [C.c_double] * 4 + [C.c_int32, P, P, C.POINTER(_ApplyOpts), P],
+                            C.c_int32),
+        "nm_spectrum_bounds": ([P, C.c_int32, C.c_uint64, P, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+                               C.c_int32),
+        "nm_filtered_eig": ([P, C.c_double, C.c_double, C.c_int32, C.c_double, C.POINTER(_EigOpts),
+                             C.POINTER(C.POINTER(_EigResult))], C.c_int32),
+        "nm_project_rotation": ([P, C.POINTER(_EigResult), C.c_double, C.c_double, P,
+                                 C.POINTER(C.POINTER(_RotResult))], C.c_int32),
+        "nm_result_copy_vectors": ([C.POINTER(_EigResult), P, C.c_int32], C.c_int32),
+        "nm_rot_copy_vectors": ([C.POINTER(_RotResult), P, C.c_int32], C.c_int32),
+        "nm_result_free": ([C.POINTER(_EigResult)], None),
+        "nm_rot_result_free": ([C.POINTER(_RotResult)], None),
+        "nm_pencil_free": ([P], None),
+        "nm_last_error": ([], C.c_char_p),
+        "nm_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(st, partial_ok=False):
+    if st == NM_OK or (partial_ok and st == NM_PARTIAL):
+        return st
+    raise NMError(st, _lib.nm_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(a.data_ptr())
+
+
+def filter_coeffs(a, b, lmin, lmax, m):
+    lib = load_library()
+    mu = np.zeros(m + 1)
+    _check(lib.nm_filter_coeffs(a, b, lmin, lmax, m, _ptr(mu)))
+    return mu
+
+
+def filter_degree(a, b, lmin, lmax, guard=1.0, mode=1):
+    """mode 0: no damping below a; 1: damping below a; 2: null factor."""
+    lib = load_library()
+    m = C.c_int32()
+    _check(lib.nm_filter_degree(a, b, lmin, lmax, guard, int(mode), C.byref(m)))
+    return m.value
+
+
+class EigResult:
+    """Eigenpairs: lam (numpy, ascending), resid (numpy), X (torch, device,
+    [n, count]) and solve statistics."""
+
+    def __init__(self, ptr, keep_vectors=True):
+        r = ptr.contents
+        self.count = r.count
+        self.lam = np.array([r.lam[i] for i in range(r.count)])
+        self.resid = np.array([r.resid[i] for i in range(r.count)])
+        self.stats = dict(degree=r.degree, kM=r.kM, kP=r.kP, block=r.block, basis=r.basis, bapps=r.bapps,
+                          lmin=r.lmin, lmax=r.lmax, seconds=r.seconds, bytes=r.bytes,
+                          filter_seconds=r.filter_seconds, hot_launches=r.hot_launches,
+                          hot_samples=r.hot_samples, hot_ms=r.hot_ms, hot_bytes=r.hot_bytes)
+        self._ptr = ptr
+        self.n = r.n
+        self.X = None
+        if keep_vectors and r.count:
+            self.X = torch.empty((r.n, r.count), dtype=torch.float64, device="cuda")
+            _check(_lib.nm_result_copy_vectors(ptr, _ptr(self.X), 1))
+
+    def __del__(self):
+        if getattr(self, "_ptr", None) is not None and _lib is not None:
+            _lib.nm_result_free(self._ptr)
+            self._ptr = None
+
+
+class RotResult:
+    def __init__(self, ptr):
+        r = ptr.contents
+        self.count = r.count
+        self.omega = np.array([r.omega[i] for i in range(r.count)])
+        self.seconds = r.seconds
+        self.U = None
+        if r.count:
+            buf = torch.empty((r.n, r.count, 2), dtype=torch.float64, device="cuda")
+            _check(_lib.nm_rot_copy_vectors(ptr, _ptr(buf), 1))
+            self.U = torch.view_as_complex(buf)
+        _lib.nm_rot_result_free(ptr)
+
+
+class Pencil:
+    """Device-resident pencil of one planet (A_G, M, R, K_p, E_G)."""
+
+    def __init__(self, planet: dict, omega=None):
+        lib = load_library()
+        xyz = np.ascontiguousarray(planet["xyz"], np.float64)
+        tet = np.ascontiguousarray(planet["tet"], np.int32)
+        reg = np.ascontiguousarray(planet["region"], np.int8)
+        order, porder = int(planet["disp_order"]), int(planet["pres_order"])
+        rho = np.ascontiguousarray(planet["rho"], np.float64)
+        lam = np.ascontiguousarray(planet["lam"], np.float64)
+        mu = np.ascontiguousarray(planet["mu"], np.float64)
+        gp, dgp = planet.get("gprime"), planet.get("grad_gprime")
+        mesh = _Mesh(len(xyz), len(tet), _ptr(xyz), _ptr(tet), _ptr(reg), order, porder)
+        keep = [xyz, tet, reg, rho, lam, mu]
+        if gp is not None:
+            gp = np.ascontiguousarray(gp, np.float64)
+            dgp = np.ascontiguousarray(dgp, np.float64)
+            keep += [gp, dgp]
+            mat = _Material(_ptr(rho), _ptr(lam), _ptr(mu), _ptr(gp), _ptr(dgp), gp.shape[1])
+        else:
+            mat = _Material(_ptr(rho), _ptr(lam), _ptr(mu), None, None, 0)
+        om = np.ascontiguousarray(planet.get("omega", (0, 0, 0)) if omega is None else omega, np.float64)
+        h = C.c_void_p()
+        _check(lib.nm_assemble(C.byref(mesh), C.byref(mat), _ptr(om), _stream(), C.byref(h)))
+        self._h = h
+        info = _Info()
+        _check(lib.nm_pencil_info_get(h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.n = self.info["n_disp"]
+        self.n_p = self.info["n_pres"]
+        self.N = self.info["n_node"]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.nm_pencil_free(self._h)
+            self._h = None
+
+    def export_csr(self, which):
+        nr, nc, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.nm_pencil_export_csr(self._h, which, C.byref(nr), C.byref(nc), C.byref(nnz), None, None, None))
+        ptr = np.zeros(nr.value + 1, np.int64)
+        col = np.zeros(max(nnz.value, 1), np.int32)
+        val = np.zeros(max(nnz.value, 1), np.float64)
+        _check(_lib.nm_pencil_export_csr(self._h, which, C.byref(nr), C.byref(nc), C.byref(nnz), _ptr(ptr),
+                                         _ptr(col), _ptr(val)))
+        return ptr, col[:nnz.value], val[:nnz.value], (nr.value, nc.value)
+
+    def nodes(self):
+        ng = np.zeros(self.N, np.int64)
+        pg = np.zeros(max(self.n_p, 1), np.int64)
+        _check(_lib.nm_pencil_nodes(self._h, _ptr(ng), _ptr(pg)))
+        return ng, pg[:self.n_p]
+
+    @staticmethod
+    def _opts(kM=0, kP=0, minv_tol=0.0, kp_tol=0.0, precision=0):
+        return _ApplyOpts(kM, kP, minv_tol, kp_tol, precision)
+
+    def apply(self, op, X, out_rows=None, **kw):
+        """Y = op(X) for a device tensor X [rows, ncols] (float64, or float32
+        with precision=1)."""
+        X = X.contiguous()
+        rows = out_rows if out_rows is not None else (self.n_p if op in (OP_EGT, OP_KP, OP_KPINV) else self.n)
+        Y = torch.empty((rows, X.shape[1]), dtype=X.dtype, device=X.device)
+        o = self._opts(**kw)
+        _check(_lib.nm_pencil_apply(self._h, op, X.shape[1], _ptr(X), _ptr(Y), C.byref(o), _stream()))
+        torch.cuda.synchronize()
+        return Y
+
+    def filter_apply(self, mu, c, e, X, null_shift=0.0, null_scale=0.0, **kw):
+        mu = np.ascontiguousarray(mu, np.float64)
+        X = X.contiguous()
+        Y = torch.empty_like(X)
+        o = self._opts(**kw)
+        _check(_lib.nm_filter_apply(self._h, _ptr(mu), len(mu) - 1, c, e, null_shift, null_scale, X.shape[1],
+                                    _ptr(X), _ptr(Y), C.byref(o), _stream()))
+        return Y
+
+    def spectrum_bounds(self, steps=60, seed=1):
+        lo, hi = C.c_double(), C.c_double()
+        _check(_lib.nm_spectrum_bounds(self._h, steps, seed, _stream(), C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def filtered_eig(self, a, b, nev, tol, degree=0, block=0, precision=0, max_basis=0, null_filter=-1,
+                     verbose=0, minv_tol=0.0, kp_tol=0.0, lmin=0.0, lmax=0.0, guard=0.0, seed=1,
+                     allow_partial=False):
+        o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, lmin, lmax,
+                     guard, seed, _stream())
+        r = C.POINTER(_EigResult)()
+        st = _lib.nm_filtered_eig(self._h, a, b, nev, tol, C.byref(o), C.byref(r))
+        if st == NM_PARTIAL and allow_partial and r:
+            res = EigResult(r)
+            res.partial = True
+            return res
+        _check(st)
+        res = EigResult(r)
+        res.partial = False
+        return res
+
+    def project_rotation(self, basis: EigResult, a, b):
+        r = C.POINTER(_RotResult)()
+        _check(_lib.nm_project_rotation(self._h, basis._ptr, a, b, _stream(), C.byref(r)))
+        return RotResult(r)

@@ -1,0 +1,323 @@
+// C ABI of the library (declared in include/nmodes.h): argument checks,
+// error codes and thread-local messages around the device code.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "nm_internal.h"
+
+namespace nm {
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+}  // namespace nm
+
+#define NM_TRY(...)                                    \
+  try {                                                \
+    nm::set_error("");                                 \
+    __VA_ARGS__;                                       \
+    return NM_OK;                                      \
+  } catch (const nm::Error& e) {                       \
+    nm::set_error(e.what());                           \
+    return e.code;                                     \
+  } catch (const std::bad_alloc&) {                    \
+    nm::set_error("host allocation failed");           \
+    return NM_ENOMEM;                                  \
+  } catch (const std::exception& e) {                  \
+    nm::set_error(e.what());                           \
+    return NM_EDEVICE;                                 \
+  }
+
+namespace {
+template <class T>
+std::vector<T> d2h(const T* d, size_t n) {
+  std::vector<T> h(n);
+  if (n) NM_HIP(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost));
+  return h;
+}
+}  // namespace
+
+static nm::ApplyCfg make_cfg(const nm_pencil* p, const nm_apply_opts* o) {
+  nm::ApplyCfg c;
+  double mt = (o && o->minv_tol > 0) ? o->minv_tol : 1e-12;
+  double pt = (o && o->kp_tol > 0) ? o->kp_tol : 1e-13;
+  c.kM = (o && o->kM > 0) ? o->kM : nm::cheb_steps(p->ref.m_lo, p->ref.m_hi, mt);
+  c.kP = (o && o->kP > 0) ? o->kP : nm::cheb_steps(p->ref.p_lo, p->ref.p_hi, pt);
+  c.precision = o ? o->precision : 0;
+  NM_REQUIRE(c.precision == 0 || c.precision == 1, NM_EINVAL, "precision must be 0 or 1");
+  NM_REQUIRE(c.kM >= 2 && c.kP >= 1, NM_EINVAL, "kM must be >= 2 and kP >= 1");
+  return c;
+}
+
+extern "C" {
+
+const char* nm_last_error(void) { return nm::g_err.c_str(); }
+const char* nm_version(void) { return "nmodes 0.1 (gfx950)"; }
+
+nm_status nm_assemble(const nm_mesh* mesh, const nm_material* mat, const double omega[3], void* stream,
+                      nm_pencil** out) {
+  NM_TRY({
+    NM_REQUIRE(mesh && mat && out, NM_EINVAL, "null argument");
+    *out = nullptr;
+    nm_pencil* P = new nm_pencil();
+    try {
+      NM_HIP(hipGetDevice(&P->device));
+      if (omega)
+        for (int i = 0; i < 3; ++i) P->omega[i] = omega[i];
+      NM_BLAS(rocblas_create_handle(&P->blas));
+      nm::assemble(P, mesh, mat, (hipStream_t)stream);
+    } catch (...) {
+      nm_pencil_free(P);
+      throw;
+    }
+    *out = P;
+  })
+}
+
+void nm_pencil_free(nm_pencil* p) {
+  if (!p) return;
+  if (p->blas) rocblas_destroy_handle(p->blas);
+  delete p;
+}
+
+nm_status nm_pencil_info_get(const nm_pencil* p, nm_pencil_info* info) {
+  NM_TRY({
+    NM_REQUIRE(p && info, NM_EINVAL, "null argument");
+    info->n_geom = p->n_geom;
+    info->n_node = p->N;
+    info->n_solid = p->n_solid;
+    info->n_disp = 3 * p->N;
+    info->n_pres = p->n_pres;
+    info->nnzb = p->nnzb;
+    info->nnz_kp = p->nnz_kp;
+    info->nnzb_eg = p->nnzb_eg;
+    info->n_fs_faces = p->n_fs;
+    info->minv_lo = p->ref.m_lo;
+    info->minv_hi = p->ref.m_hi;
+    info->kp_lo = p->ref.p_lo;
+    info->kp_hi = p->ref.p_hi;
+  })
+}
+
+
+nm_status nm_pencil_export_csr(const nm_pencil* p, int32_t which, int64_t* nrows, int64_t* ncols, int64_t* nnz,
+                               int64_t* row_ptr, int32_t* col, double* val) {
+  NM_TRY({
+    NM_REQUIRE(p && nrows && ncols && nnz, NM_EINVAL, "null argument");
+    const int64_t N = p->N, n = 3 * N, NP = p->n_pres;
+    switch (which) {
+      case NM_MAT_AG: case NM_MAT_R: *nrows = n; *ncols = n; *nnz = 9 * p->nnzb; break;
+      case NM_MAT_M: *nrows = N; *ncols = N; *nnz = p->nnzb; break;
+      case NM_MAT_KP: *nrows = NP; *ncols = NP; *nnz = p->nnz_kp; break;
+      case NM_MAT_EG: *nrows = n; *ncols = NP; *nnz = NP ? 3 * p->nnzb_eg : 0; break;
+      default: throw nm::Error(NM_EINVAL, "unknown matrix id");
+    }
+    if (!row_ptr) return NM_OK;
+    NM_REQUIRE(col, NM_EINVAL, "col buffer missing");
+    if (which == NM_MAT_KP) {
+      if (NP == 0) { row_ptr[0] = 0; return NM_OK; }
+      auto rp = d2h(p->kp_ptr.p, NP + 1);
+      auto c = d2h(p->kp_col.p, *nnz);
+      for (int64_t i = 0; i <= NP; ++i) row_ptr[i] = rp[i];
+      std::memcpy(col, c.data(), 4 * c.size());
+      if (val) {
+        auto v = d2h(p->kp.p, *nnz);
+        std::memcpy(val, v.data(), 8 * v.size());
+      }
+      return NM_OK;
+    }
+    // displacement rows are stored in the internal (Morton) node order:
+    // canonical row c is internal row perm[c], internal column j is
+    // canonical column iperm[j]; entries are re-sorted by canonical column
+    auto perm = d2h(p->perm.p, N);
+    auto iperm = d2h(p->iperm.p, N);
+    if (which == NM_MAT_EG) {
+      if (NP == 0) { for (int64_t i = 0; i <= n; ++i) row_ptr[i] = 0; return NM_OK; }
+      auto rp = d2h(p->eg_ptr.p, N + 1);
+      auto c = d2h(p->eg_col.p, p->nnzb_eg);
+      std::vector<double> v;
+      if (val) v = d2h(p->eg_val.p, 3 * p->nnzb_eg);
+      int64_t q = 0;
+      row_ptr[0] = 0;
+      for (int64_t cr = 0; cr < N; ++cr) {
+        const int64_t i = perm[cr];
+        for (int cc = 0; cc < 3; ++cc) {
+          for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {  // pressure columns are canonical and sorted
+            col[q] = c[k];
+            if (val) val[q] = v[3 * (int64_t)k + cc];
+            ++q;
+          }
+          row_ptr[3 * cr + cc + 1] = q;
+        }
+      }
+      return NM_OK;
+    }
+    auto rp = d2h(p->row_ptr.p, N + 1);
+    auto c = d2h(p->col.p, p->nnzb);
+    std::vector<double> v;
+    const bool ag = which == NM_MAT_AG;
+    if (val) v = d2h(ag ? p->ag.p : p->ms.p, ag ? 9 * p->nnzb : p->nnzb);
+    const double* om = p->omega;
+    const double Ox[3][3] = {{0, -om[2], om[1]}, {om[2], 0, -om[0]}, {-om[1], om[0], 0}};
+    std::vector<std::pair<int32_t, int32_t>> ent;  // (canonical col, internal entry)
+    int64_t q = 0;
+    row_ptr[0] = 0;
+    for (int64_t cr = 0; cr < N; ++cr) {
+      const int64_t i = perm[cr];
+      ent.clear();
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) ent.emplace_back(iperm[c[k]], k);
+      std::sort(ent.begin(), ent.end());
+      if (which == NM_MAT_M) {
+        for (auto& pr : ent) {
+          col[q] = pr.first;
+          if (val) val[q] = v[pr.second];
+          ++q;
+        }
+        row_ptr[cr + 1] = q;
+        continue;
+      }
+      for (int cc = 0; cc < 3; ++cc) {
+        for (auto& pr : ent)
+          for (int d = 0; d < 3; ++d) {
+            col[q] = 3 * pr.first + d;
+            if (val) val[q] = ag ? v[9 * (int64_t)pr.second + 3 * cc + d] : v[pr.second] * Ox[cc][d];
+            ++q;
+          }
+        row_ptr[3 * cr + cc + 1] = q;
+      }
+    }
+  })
+}
+
+nm_status nm_pencil_nodes(const nm_pencil* p, int64_t* node_geom, int64_t* pres_geom) {
+  NM_TRY({
+    NM_REQUIRE(p, NM_EINVAL, "null pencil");
+    if (node_geom) {
+      auto h = d2h(p->node_geom.p, p->N);
+      for (int64_t i = 0; i < p->N; ++i) node_geom[i] = h[i];
+    }
+    if (pres_geom && p->n_pres) {
+      auto h = d2h(p->pres_geom.p, p->n_pres);
+      for (int64_t i = 0; i < p->n_pres; ++i) pres_geom[i] = h[i];
+    }
+  })
+}
+
+
+nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const void* X, void* Y,
+                          const nm_apply_opts* opts, void* stream) {
+  NM_TRY({
+    NM_REQUIRE(p && X && Y && X != Y, NM_EINVAL, "invalid pointers");
+    nm::api_apply(p, op, ncols, X, Y, make_cfg(p, opts), (hipStream_t)stream);
+  })
+}
+
+nm_status nm_filter_coeffs(double a, double b, double lmin, double lmax, int32_t m, double* mu) {
+  NM_TRY({
+    NM_REQUIRE(mu && m >= 0 && lmax > lmin && b > a, NM_EINVAL, "invalid filter arguments");
+    nm::jackson_chebyshev(a, b, lmin, lmax, m, mu);
+  })
+}
+
+nm_status nm_filter_degree(double a, double b, double lmin, double lmax, double guard, int32_t null_filter,
+                           int32_t* m) {
+  NM_TRY({
+    NM_REQUIRE(m && lmax > lmin && b > a, NM_EINVAL, "invalid filter arguments");
+    NM_REQUIRE(null_filter >= 0 && null_filter <= 2, NM_EINVAL, "mode must be 0, 1 or 2");
+    *m = nm::choose_degree(a, b, lmin, lmax, guard, null_filter);
+  })
+}
+
+nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, double c, double e, double null_shift,
+                          double null_scale, int32_t ncols, const void* X, void* Y, const nm_apply_opts* opts,
+                          void* stream) {
+  NM_TRY({
+    NM_REQUIRE(p && mu && X && Y && X != Y && m >= 0 && e > 0 && ncols > 0, NM_EINVAL, "invalid filter arguments");
+    auto cfg = make_cfg(p, opts);
+    hipStream_t st = (hipStream_t)stream;
+    // vectors cross the ABI in canonical node order; the filter runs in the internal order
+    const int eb = cfg.precision == 1 ? 4 : 8;
+    const int64_t w = 3 * (int64_t)ncols;
+    nm::DBuf<char> xi((size_t)p->N * w * eb), yi((size_t)p->N * w * eb);
+    nm::permute_rows(p->N, (int)w, X, xi.p, p->iperm.p, eb, st);
+    if (cfg.precision == 1) {
+      const_cast<nm_pencil*>(p)->ensure_fp32(st);
+      nm::FilterWork<float> wk;
+      nm::filter_apply<float>(p, mu, m, c, e, null_shift, null_scale, ncols, (const float*)xi.p, (float*)yi.p, cfg,
+                              wk, st);
+    } else {
+      nm::FilterWork<double> wk;
+      nm::filter_apply<double>(p, mu, m, c, e, null_shift, null_scale, ncols, (const double*)xi.p, (double*)yi.p,
+                               cfg, wk, st);
+    }
+    nm::permute_rows(p->N, (int)w, yi.p, Y, p->perm.p, eb, st);
+    NM_HIP(hipStreamSynchronize(st));
+    NM_HIP(hipGetLastError());
+  })
+}
+
+nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, void* stream, double* lmin,
+                             double* lmax) {
+  NM_TRY({
+    NM_REQUIRE(p && lmin && lmax && steps >= 2, NM_EINVAL, "invalid arguments");
+    nm::spectrum_bounds(p, steps, seed, (hipStream_t)stream, lmin, lmax);
+  })
+}
+
+nm_status nm_filtered_eig(const nm_pencil* p, double a, double b, int32_t nev, double tol, const nm_eig_opts* opts,
+                          nm_eig_result** out) {
+  NM_TRY({
+    NM_REQUIRE(p && out, NM_EINVAL, "null argument");
+    *out = nullptr;
+    nm_eig_opts o;
+    if (opts) o = *opts;
+    else {
+      std::memset(&o, 0, sizeof(o));
+      o.null_filter = -1;
+    }
+    nm::filtered_eig(p, a, b, nev, tol, o, out);
+  })
+}
+
+nm_status nm_project_rotation(const nm_pencil* p, const nm_eig_result* basis, double a, double b, void* stream,
+                              nm_rot_result** out) {
+  NM_TRY({
+    NM_REQUIRE(p && basis && out && b > a, NM_EINVAL, "invalid arguments");
+    *out = nullptr;
+    nm::project_rotation(p, basis, a, b, (hipStream_t)stream, out);
+  })
+}
+
+nm_status nm_result_copy_vectors(const nm_eig_result* r, void* dst, int32_t dst_is_device) {
+  NM_TRY({
+    NM_REQUIRE(r && dst, NM_EINVAL, "null argument");
+    if (r->count)
+      NM_HIP(hipMemcpy(dst, r->X, 8 * (size_t)r->n * r->count,
+                       dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  })
+}
+
+nm_status nm_rot_copy_vectors(const nm_rot_result* r, void* dst, int32_t dst_is_device) {
+  NM_TRY({
+    NM_REQUIRE(r && dst, NM_EINVAL, "null argument");
+    if (r->count)
+      NM_HIP(hipMemcpy(dst, r->U, 16 * (size_t)r->n * r->count,
+                       dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  })
+}
+
+void nm_result_free(nm_eig_result* r) {
+  if (!r) return;
+  if (r->X) (void)hipFree(r->X);
+  std::free(r->lambda);
+  std::free(r->resid);
+  delete r;
+}
+
+void nm_rot_result_free(nm_rot_result* r) {
+  if (!r) return;
+  if (r->U) (void)hipFree(r->U);
+  std::free(r->omega);
+  std::free(r);
+}
+
+}  // extern "C"

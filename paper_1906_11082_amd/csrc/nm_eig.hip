@@ -1,0 +1,652 @@
+// Polynomial-filtered block Lanczos for the Cowling pencil (Sec. 6.1 of the
+// paper: polynomial filtering on [f1, f2], A and M accessed through
+// products; filter and Lanczos details follow the cited EVSL approach).
+//
+//  * spectrum bounds of B = M^{-1} A: a short Lanczos in the M-inner product;
+//  * filter: Jackson-damped Chebyshev series of the window indicator,
+//    optionally times (B - lambda_0)/s, which annihilates an exactly
+//    degenerate null space (rigid motions, the fluid kernel of the
+//    Cowling operator with N^2 = 0) without resolving the gap below the
+//    window;
+//  * block Krylov on p(B) in the M-inner product with full, twice-iterated
+//    block Gram-Schmidt and Cholesky QR (twice), keeping A V;
+//  * Rayleigh-Ritz with the original pencil (A, M) on the basis; stop when
+//    every Ritz pair in the window has residual <= tol, their count is
+//    stable and every Ritz value of p(B) above the filter's window level
+//    has converged.
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <cmath>
+#include <numeric>
+
+#include "nm_internal.h"
+
+namespace nm {
+
+// ------------------------------------------------------------ filter design
+void jackson_chebyshev(double a, double b, double lmin, double lmax, int m, double* mu) {
+  const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
+  double al = std::min(1.0, std::max(-1.0, (a - c) / e));
+  double be = std::min(1.0, std::max(-1.0, (b - c) / e));
+  const double ta = std::acos(al), tb = std::acos(be);
+  const double th = M_PI / (m + 2);
+  for (int k = 0; k <= m; ++k) {
+    double gam = k == 0 ? (ta - tb) / M_PI : 2.0 * (std::sin(k * ta) - std::sin(k * tb)) / (M_PI * k);
+    double jac = ((1.0 - (double)k / (m + 2)) * std::sin(th) * std::cos(k * th) +
+                  std::cos(th) * std::sin(k * th) / (m + 2)) / std::sin(th);
+    mu[k] = gam * jac;
+  }
+}
+
+double cheb_eval(const double* mu, int m, double t) {
+  double t0 = 1.0, t1 = t, s = mu[0] + (m >= 1 ? mu[1] * t : 0.0);
+  for (int k = 2; k <= m; ++k) {
+    double t2 = 2.0 * t * t1 - t0;
+    s += mu[k] * t2;
+    t0 = t1;
+    t1 = t2;
+  }
+  return s;
+}
+
+namespace {
+double filter_value(const std::vector<double>& mu, int m, double c, double e, double lam, bool null, double s0) {
+  double p = cheb_eval(mu.data(), m, std::min(1.0, std::max(-1.0, (lam - c) / e)));
+  return null ? p * lam / s0 : p;
+}
+}  // namespace
+
+// Smallest degree (on a 15 % ladder) whose filter stays below 1 % of its
+// window-edge level beyond the guard point b (1 + guard); lower side:
+//   mode 0  no requirement below a.  For the Cowling pencil with N^2 = 0 the
+//           spectrum below the window is the exactly degenerate fluid null
+//           space (plus rigid motions): a Krylov method sees a degenerate
+//           eigenvalue as one direction per start vector, so it needs no
+//           damping; the few other low modes converge as unwanted pairs.
+//   mode 1  the same bound below a - guard (a - lmin);
+//   mode 2  the filter is multiplied by lambda / b (null factor).
+int choose_degree(double a, double b, double lmin, double lmax, double guard, int mode) {
+  if (guard <= 0) guard = 1.0;
+  const bool null = mode == 2;
+  const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
+  const double bg = b * (1.0 + guard);
+  const double ag = a - guard * std::max(a - lmin, 0.0);
+  const double s0 = null ? b : 0.0;
+  std::vector<double> mu;
+  for (double md = 8; md < 20000; md *= 1.15) {
+    int m = (int)md;
+    mu.resize(m + 1);
+    jackson_chebyshev(a, b, lmin, lmax, m, mu.data());
+    double pa = filter_value(mu, m, c, e, a, null, s0), pb = filter_value(mu, m, c, e, b, null, s0);
+    double lev = std::min(pa, pb);
+    if (!(lev > 0)) continue;
+    bool ok = true;
+    // sample uniformly in angle, which resolves the polynomial's oscillations
+    const int ns = 4 * m + 64;
+    double th_hi = std::acos(std::min(1.0, std::max(-1.0, (bg - c) / e)));
+    for (int i = 0; i <= ns && ok && bg < lmax; ++i) {
+      double th = th_hi * i / ns;
+      double lam = c + e * std::cos(th);
+      if (std::fabs(filter_value(mu, m, c, e, lam, null, s0)) > 0.01 * lev) ok = false;
+    }
+    if (mode == 1 && ag > lmin) {
+      double th_lo = std::acos(std::min(1.0, std::max(-1.0, (ag - c) / e)));
+      for (int i = 0; i <= ns && ok; ++i) {
+        double th = th_lo + (M_PI - th_lo) * i / ns;
+        double lam = c + e * std::cos(th);
+        if (std::fabs(filter_value(mu, m, c, e, lam, null, s0)) > 0.01 * lev) ok = false;
+      }
+    }
+    if (ok) return m;
+  }
+  throw Error(NM_EINVAL, "no filter degree below 20000 separates the window");
+}
+
+namespace {
+
+__device__ __forceinline__ int64_t gtid() { return nm_xcd_block() * blockDim.x + threadIdx.x; }
+
+// counter-based N(0,1): splitmix64 hash of (seed, column, row), Box-Muller
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_randn(int64_t rows, int nc, int ld, uint64_t seed, int64_t col0, double* X) {
+  int64_t g = gtid();
+  if (g >= rows * nc) return;
+  int64_t r = g / nc;
+  int v = (int)(g % nc);
+  uint64_t h = mix64(mix64(seed ^ mix64((uint64_t)(col0 + v) * 0x632BE59BD9B4E019ull)) ^ (uint64_t)r);
+  uint64_t h2 = mix64(h);
+  double u1 = ((h >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+  double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  X[r * ld + v] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+__global__ void k_sub_scaled_cols(int64_t rows, int nc, const double* __restrict__ AX,
+                                  const double* __restrict__ MX, const double* __restrict__ th,
+                                  double* __restrict__ R) {
+  int64_t g = gtid();
+  if (g >= rows * nc) return;
+  int v = (int)(g % nc);
+  R[g] = AX[g] - th[v] * MX[g];
+}
+
+// per column: index of the entry of largest magnitude -> sign
+__global__ void k_col_sign(int64_t rows, int nc, const double* __restrict__ X, double* __restrict__ sgn) {
+  int v = blockIdx.x;
+  __shared__ double bv[256];
+  double best = 0.0, val = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+    double x = X[r * nc + v];
+    if (fabs(x) > best) { best = fabs(x); val = x; }
+  }
+  // reduce by magnitude, ties resolved toward the smaller thread (row order)
+  __shared__ double bm[256];
+  bm[threadIdx.x] = best;
+  bv[threadIdx.x] = val;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o && bm[threadIdx.x + o] > bm[threadIdx.x]) {
+      bm[threadIdx.x] = bm[threadIdx.x + o];
+      bv[threadIdx.x] = bv[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn[v] = bv[0] < 0 ? -1.0 : 1.0;
+}
+__global__ void k_scale_cols(int64_t rows, int nc, const double* __restrict__ s, double* __restrict__ X) {
+  int64_t g = gtid();
+  if (g >= rows * nc) return;
+  X[g] *= s[g % nc];
+}
+
+struct Blas {
+  rocblas_handle h;
+  // row-major helpers expressed through column-major GEMM
+  // C[K][q] (col-major K x q, ld K) = A^T B, A row-major [n][*] (ld lda, first K cols), B row-major [n][*] (q cols)
+  void tn(int64_t n, int K, int q, const double* A, int lda, const double* B, int ldb, double* C, double alpha = 1.0,
+          double beta = 0.0) {
+    NM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, q, (rocblas_int)n, &alpha, A,
+                          lda, B, ldb, &beta, C, K));
+  }
+  // D (row-major [n][q], ld ldd) = alpha * A (row-major [n][K], ld lda) * C (col-major K x q, ld ldc) + beta * D
+  void nn(int64_t n, int K, int q, double alpha, const double* A, int lda, const double* C, int ldc, double beta,
+          double* D, int ldd) {
+    NM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, q, (rocblas_int)n, K, &alpha, C,
+                          ldc, A, lda, &beta, D, ldd));
+  }
+};
+
+void chol_upper(int b, std::vector<double>& G, bool& ok) {
+  // in place: G (col-major b x b, symmetric) -> R upper with G = R^T R
+  ok = true;
+  for (int j = 0; j < b; ++j) {
+    double s = G[j + j * b];
+    for (int k = 0; k < j; ++k) s -= G[k + j * b] * G[k + j * b];
+    if (!(s > 0)) { ok = false; return; }
+    double r = std::sqrt(s);
+    G[j + j * b] = r;
+    for (int i = j + 1; i < b; ++i) {
+      double t = G[j + i * b];
+      for (int k = 0; k < j; ++k) t -= G[k + j * b] * G[k + i * b];
+      G[j + i * b] = t / r;
+    }
+    for (int i = j + 1; i < b; ++i) G[i + j * b] = 0.0;
+  }
+}
+
+void upper_inverse(int b, const std::vector<double>& R, std::vector<double>& Ri) {
+  Ri.assign(b * b, 0.0);
+  for (int j = 0; j < b; ++j) {
+    Ri[j + j * b] = 1.0 / R[j + j * b];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0;
+      for (int k = i + 1; k <= j; ++k) s += R[i + k * b] * Ri[k + j * b];
+      Ri[i + j * b] = -s / R[i + i * b];
+    }
+  }
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double s() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+}  // namespace
+
+// Bounds of spec(M^{-1} A) from `steps` Lanczos steps in the M-inner
+// product (full reorthogonalisation): lmax = 1.01 (theta_max + |beta s|),
+// a safe upper bound once the top Ritz value has converged;
+// lmin = min(0, theta_min) - min(|beta s|_min, |theta_min| + 1e-12): the
+// bottom of the spectrum (rigid motions, the fluid null space) is dense and
+// converges slowly, and an estimate a little above the true minimum only
+// lets the Chebyshev polynomials grow mildly there.
+void spectrum_bounds(const nm_pencil* P, int steps_req, uint64_t seed, hipStream_t st, double* lmin_out,
+                     double* lmax_out) {
+  const int64_t n = 3 * P->N;
+  const int steps = (int)std::min<int64_t>(steps_req, n - 1);
+  NM_REQUIRE(steps >= 2, NM_EINVAL, "problem too small for spectrum bounds");
+  Blas bl{P->blas};
+  NM_BLAS(rocblas_set_stream(bl.h, st));
+  NM_BLAS(rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host));
+  ApplyCfg bc;
+  bc.precision = 0;
+  bc.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, 1e-12);
+  bc.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, 1e-13);
+  FilterWork<double> w1;
+  DBuf<double> Vl((size_t)n * (steps + 1)), z(n), mz(n), dots(std::max(steps + 1, 2));
+  hipLaunchKernelGGL(k_randn, dim3(grid_for(n)), dim3(256), 0, st, n, 1, 1, seed, 0, Vl.p);
+  std::vector<double> al, be;
+  const double one = 1.0, zero = 0.0, m1 = -1.0;
+  auto mnorm = [&](const double* v) {
+    apply_op(P, NM_OP_M, 1, v, mz.p, bc, st);
+    double d;
+    col_dots(n, 1, v, 1, mz.p, 1, dots.p, st);
+    NM_HIP(hipMemcpy(&d, dots.p, 8, hipMemcpyDeviceToHost));
+    return std::sqrt(std::max(d, 0.0));
+  };
+  double inv = 1.0 / mnorm(Vl.p);
+  NM_BLAS(rocblas_dscal(bl.h, (rocblas_int)n, &inv, Vl.p, 1));
+  for (int k = 0; k < steps; ++k) {
+    double* v = Vl.p + (size_t)k * n;
+    b_apply<double>(P, 1, v, z.p, bc, w1, st);
+    for (int pass = 0; pass < 2; ++pass) {
+      apply_op(P, NM_OP_M, 1, z.p, mz.p, bc, st);
+      std::vector<double> h(k + 1);
+      NM_BLAS(rocblas_dgemv(bl.h, rocblas_operation_transpose, (rocblas_int)n, k + 1, &one, Vl.p, (rocblas_int)n,
+                            mz.p, 1, &zero, dots.p, 1));
+      NM_HIP(hipMemcpyAsync(h.data(), dots.p, 8 * (k + 1), hipMemcpyDeviceToHost, st));
+      NM_HIP(hipStreamSynchronize(st));
+      if (pass == 0) al.push_back(h[k]);
+      else al.back() += h[k];
+      NM_BLAS(rocblas_dgemv(bl.h, rocblas_operation_none, (rocblas_int)n, k + 1, &m1, Vl.p, (rocblas_int)n, dots.p, 1,
+                            &one, z.p, 1));
+    }
+    double bt = mnorm(z.p);
+    be.push_back(bt);
+    if (!(bt > 1e-12 * std::fabs(al.back())) || !std::isfinite(bt)) break;
+    double ib = 1.0 / bt;
+    NM_HIP(hipMemcpyAsync(Vl.p + (size_t)(k + 1) * n, z.p, 8 * n, hipMemcpyDeviceToDevice, st));
+    NM_BLAS(rocblas_dscal(bl.h, (rocblas_int)n, &ib, Vl.p + (size_t)(k + 1) * n, 1));
+  }
+  int m = (int)al.size();
+  std::vector<double> Tm(m * m, 0.0), th, S;
+  for (int i = 0; i < m; ++i) {
+    Tm[i + i * m] = al[i];
+    if (i + 1 < m) Tm[i + (i + 1) * m] = Tm[(i + 1) + i * m] = be[i];
+  }
+  jacobi_eig(m, Tm, th, &S);
+  double rmax = std::fabs(be[m - 1] * S[(m - 1) + (m - 1) * m]);
+  double rmin = std::fabs(be[m - 1] * S[(m - 1) + 0 * m]);
+  NM_REQUIRE(std::isfinite(th[m - 1]) && std::isfinite(rmax), NM_ENOCONV, "non-finite Lanczos bounds");
+  *lmax_out = (th[m - 1] + rmax) * 1.01;
+  *lmin_out = std::min(0.0, th[0]) - std::min(rmin, std::fabs(th[0]) + 1e-12);
+}
+
+void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
+                  nm_eig_result** out) {
+  NM_REQUIRE(b > a && nev > 0 && tol > 0, NM_EINVAL, "need a < b, nev > 0, tol > 0");
+  hipStream_t st = (hipStream_t)o.stream;
+  Timer clock;
+  const int64_t N = P->N, n = 3 * N;
+  const int prec = o.precision;
+  NM_REQUIRE(prec == 0 || prec == 1, NM_EINVAL, "precision must be 0 or 1");
+  if (prec == 1) const_cast<nm_pencil*>(P)->ensure_fp32(st);
+  int bs = o.block > 0 ? o.block : 16;
+  bs = (int)std::min<int64_t>(bs, n);
+  int Kmax = o.max_basis > 0 ? o.max_basis
+                            : (int)std::min<int64_t>(n, std::max({6 * nev, nev + 16 * bs, 320}));
+  Kmax = std::max(Kmax / bs, 2) * bs;
+  Kmax = (int)std::min<int64_t>(Kmax, n / bs * bs);
+  NM_REQUIRE(Kmax >= 2 * bs, NM_EINVAL, "problem too small for the block size");
+
+  ApplyCfg cfg;
+  KernelProf prof;
+  cfg.prof = &prof;
+  double mtol = o.minv_tol > 0 ? o.minv_tol : (prec ? 1e-7 : 1e-10);
+  double ptol = o.kp_tol > 0 ? o.kp_tol : (prec ? 1e-7 : 1e-13);
+  cfg.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, mtol);
+  cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, ptol);
+  cfg.precision = prec;
+  Blas bl{P->blas};
+  NM_BLAS(rocblas_set_stream(bl.h, st));
+  NM_BLAS(rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host));
+
+  // ---------------- spectrum bounds (FP64 Lanczos in the M-inner product)
+  double lmin = o.lmin, lmax = o.lmax;
+  if (!(lmax > lmin)) {
+    spectrum_bounds(P, 60, o.seed ^ 0x5bd1e995ull, st, &lmin, &lmax);
+    lmin -= 1e-3 * (b - a);
+  }
+  NM_REQUIRE(lmax > b, NM_EINVAL, "window lies above the spectrum (b >= lambda_max)");
+
+  // ---------------- filter
+  // lower-side treatment (see choose_degree): explicit null factor, or,
+  // by default, no damping below a when the pencil has fluid (its spectrum
+  // below the window is the exactly degenerate Cowling null space) and
+  // damping below a otherwise
+  int mode = o.null_filter == 1 ? 2 : (o.null_filter == 0 ? 1 : (P->n_pres > 0 ? 0 : 1));
+  if (o.null_filter == 2) mode = 0;
+  const bool null = mode == 2;
+  const double l0 = 0.0, s0 = null ? b : 0.0;
+  const int m = o.degree > 0 ? o.degree : choose_degree(a, b, lmin, lmax, o.guard, mode);
+  std::vector<double> mu(m + 1);
+  jackson_chebyshev(a, b, lmin, lmax, m, mu.data());
+  const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
+  const double tau = std::min(filter_value(mu, m, c, e, a, null, s0), filter_value(mu, m, c, e, b, null, s0));
+
+  // ---------------- basis
+  DBuf<double> V((size_t)n * Kmax), AV((size_t)n * Kmax);
+  DBuf<double> W((size_t)n * bs), MW((size_t)n * bs), T2((size_t)n * bs), Cd((size_t)Kmax * bs),
+      Gd((size_t)bs * bs);
+  FilterWork<double> fw;
+  FilterWork<float> fw32;
+  DBuf<float> x32, y32;
+  if (prec) {
+    x32.alloc((size_t)n * bs);
+    y32.alloc((size_t)n * bs);
+  }
+  std::vector<double> H((size_t)Kmax * Kmax, 0.0);  // Arnoldi coefficients of p(B), col-major
+  double filter_time = 0.0, bytes = 0.0;
+  int64_t bapps = 0;
+
+  // FP64 operators of the pencil itself (Rayleigh-Ritz, residuals, M-inner products)
+  ApplyCfg cfg64;
+  cfg64.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, 1e-12);
+  cfg64.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, 1e-13);
+  cfg64.precision = 0;
+  auto mprod = [&](const double* X, double* Y, int nc) { apply_op(P, NM_OP_M, nc, X, Y, cfg64, st); };
+  // orthogonalise W (n x bs) against V[:, :K] (twice) and M-normalise by Cholesky QR (twice);
+  // returns false on rank deficiency
+  auto orthonormalise = [&](int K, double* Hcol, double* Rblk) -> bool {
+    std::vector<double> Ch((size_t)std::max(K, 1) * bs);
+    for (int pass = 0; pass < 2 && K > 0; ++pass) {
+      mprod(W.p, MW.p, bs);
+      bl.tn(n, K, bs, V.p, Kmax, MW.p, bs, Cd.p);
+      bl.nn(n, K, bs, -1.0, V.p, Kmax, Cd.p, K, 1.0, W.p, bs);
+      if (Hcol) {
+        NM_HIP(hipMemcpyAsync(Ch.data(), Cd.p, 8 * (size_t)K * bs, hipMemcpyDeviceToHost, st));
+        NM_HIP(hipStreamSynchronize(st));
+        for (int v = 0; v < bs; ++v)
+          for (int i = 0; i < K; ++i) Hcol[(size_t)i + (size_t)v * Kmax] += Ch[i + (size_t)v * K];
+      }
+    }
+    std::vector<double> Rtot(bs * bs, 0.0);
+    for (int i = 0; i < bs; ++i) Rtot[i + i * bs] = 1.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      mprod(W.p, MW.p, bs);
+      bl.tn(n, bs, bs, W.p, bs, MW.p, bs, Gd.p);
+      std::vector<double> G(bs * bs), Ri;
+      NM_HIP(hipMemcpyAsync(G.data(), Gd.p, 8 * bs * bs, hipMemcpyDeviceToHost, st));
+      NM_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < i; ++j) G[i + j * bs] = G[j + i * bs] = 0.5 * (G[i + j * bs] + G[j + i * bs]);
+      double gmax = 0;
+      for (int i = 0; i < bs; ++i) gmax = std::max(gmax, G[i + i * bs]);
+      bool ok;
+      chol_upper(bs, G, ok);
+      if (!ok) return false;
+      double rmin = 1e300;
+      for (int i = 0; i < bs; ++i) rmin = std::min(rmin, G[i + i * bs]);
+      if (rmin * rmin < 1e-24 * gmax) return false;
+      upper_inverse(bs, G, Ri);
+      NM_HIP(hipMemcpyAsync(Gd.p, Ri.data(), 8 * bs * bs, hipMemcpyHostToDevice, st));
+      bl.nn(n, bs, bs, 1.0, W.p, bs, Gd.p, bs, 0.0, T2.p, bs);
+      std::swap(W.p, T2.p);
+      // Rtot = R_pass * Rtot
+      std::vector<double> Rn(bs * bs, 0.0);
+      for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < bs; ++j) {
+          double s = 0;
+          for (int k = 0; k < bs; ++k) s += G[i + k * bs] * Rtot[k + j * bs];
+          Rn[i + j * bs] = s;
+        }
+      Rtot = Rn;
+    }
+    if (Rblk) std::copy(Rtot.begin(), Rtot.end(), Rblk);
+    return true;
+  };
+  auto put_block = [&](int K) {
+    NM_HIP(hipMemcpy2DAsync(V.p + K, 8 * (size_t)Kmax, W.p, 8 * (size_t)bs, 8 * (size_t)bs, n,
+                            hipMemcpyDeviceToDevice, st));
+    apply_op(P, NM_OP_A, bs, W.p, MW.p, cfg64, st);
+    NM_HIP(hipMemcpy2DAsync(AV.p + K, 8 * (size_t)Kmax, MW.p, 8 * (size_t)bs, 8 * (size_t)bs, n,
+                            hipMemcpyDeviceToDevice, st));
+  };
+
+  uint64_t seed = o.seed;
+  int64_t fresh = 0;
+  auto random_block = [&]() {
+    hipLaunchKernelGGL(k_randn, dim3(grid_for(n * bs)), dim3(256), 0, st, n, bs, bs, seed, fresh, W.p);
+    fresh += bs;
+  };
+  random_block();
+  NM_REQUIRE(orthonormalise(0, nullptr, nullptr), NM_ENOCONV, "start block is rank deficient");
+  put_block(0);
+  int K = bs;  // columns in V
+
+  // results of the last Rayleigh-Ritz
+  std::vector<double> th_sel, res_sel;
+  std::vector<int> idx_sel;
+  DBuf<double> HA, th_d, ework;
+  DBuf<rocblas_int> info(1);
+  int last_count = -1;
+  bool converged = false;
+  int Kc_last = 0;
+  std::vector<double> Ysel;  // col-major Kc x nsel
+
+  for (int j = 0;; ++j) {
+    const int Kj = K - bs;  // first column of the block to filter
+    // ---- filter
+    Timer ft;
+    const double* vj = nullptr;
+    if (prec == 0) {
+      fw.ensure(P, bs);
+      NM_HIP(hipMemcpy2DAsync(fw.x0.p, 8 * (size_t)bs, V.p + Kj, 8 * (size_t)Kmax, 8 * (size_t)bs, n,
+                              hipMemcpyDeviceToDevice, st));
+      vj = fw.x0.p;
+      filter_apply<double>(P, mu.data(), m, c, e, l0, s0, bs, vj, W.p, cfg, fw, st);
+    } else {
+      fw32.ensure(P, bs);
+      NM_HIP(hipMemcpy2DAsync(T2.p, 8 * (size_t)bs, V.p + Kj, 8 * (size_t)Kmax, 8 * (size_t)bs, n,
+                              hipMemcpyDeviceToDevice, st));
+      convert_f64_f32(n * bs, T2.p, x32.p, st);
+      filter_apply<float>(P, mu.data(), m, c, e, l0, s0, bs, x32.p, y32.p, cfg, fw32, st);
+      convert_f32_f64(n * bs, y32.p, W.p, st);
+    }
+    NM_HIP(hipStreamSynchronize(st));
+    filter_time += ft.s();
+    const int napp = m + (null ? 1 : 0);
+    bapps += (int64_t)napp * bs;
+    {
+      // algorithmic bytes of one column B-application (matrices amortised over bs columns)
+      const double s = prec ? 4.0 : 8.0;
+      const double nnzb = (double)P->nnzb;
+      double per = (nnzb * (9 * s + 4) + (cfg.kM - 1) * nnzb * (s + 4)) / bs + (4.0 * (cfg.kM - 1) + 4.0) * n * s;
+      bytes += per * napp * bs;
+    }
+    // ---- blow-up guard
+    {
+      std::vector<double> nr(bs);
+      mprod(W.p, MW.p, bs);
+      col_dots(n, bs, W.p, bs, MW.p, bs, Gd.p, st);
+      NM_HIP(hipMemcpy(nr.data(), Gd.p, 8 * bs, hipMemcpyDeviceToHost));
+      for (double x : nr)
+        if (!std::isfinite(x) || x > 1e30)
+          throw Error(NM_ENOCONV, "filter blow-up: the spectrum bound lambda_max is too small");
+    }
+    if (K + bs > Kmax) break;
+    // ---- orthogonalise, extend the basis
+    std::vector<double> Rb(bs * bs);
+    bool ok = orthonormalise(K, H.data() + (size_t)Kj * Kmax, Rb.data());
+    if (ok) {
+      for (int v = 0; v < bs; ++v)
+        for (int i = 0; i < bs; ++i) H[(size_t)(K + i) + (size_t)(Kj + v) * Kmax] = Rb[i + v * bs];
+    } else {
+      // breakdown: the filtered space is (numerically) invariant; restart with fresh directions
+      for (int tries = 0; tries < 3 && !ok; ++tries) {
+        random_block();
+        ok = orthonormalise(K, nullptr, nullptr);
+      }
+      NM_REQUIRE(ok, NM_ENOCONV, "block Lanczos breakdown could not be recovered");
+    }
+    put_block(K);
+    K += bs;
+
+    // ---- Rayleigh-Ritz with (A, M) on V[:, :K]
+    const int Kc = K;
+    if (Kc < 2 * bs && Kc + bs <= Kmax) continue;
+    HA.alloc((size_t)Kc * Kc);
+    th_d.alloc(Kc);
+    ework.alloc(Kc);
+    bl.tn(n, Kc, Kc, V.p, Kmax, AV.p, Kmax, HA.p);
+    {
+      std::vector<double> h((size_t)Kc * Kc);
+      NM_HIP(hipMemcpyAsync(h.data(), HA.p, 8 * h.size(), hipMemcpyDeviceToHost, st));
+      NM_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < Kc; ++i)
+        for (int q = 0; q < i; ++q) h[i + (size_t)q * Kc] = h[q + (size_t)i * Kc] = 0.5 * (h[i + (size_t)q * Kc] + h[q + (size_t)i * Kc]);
+      NM_HIP(hipMemcpyAsync(HA.p, h.data(), 8 * h.size(), hipMemcpyHostToDevice, st));
+    }
+    NM_BLAS(rocsolver_dsyevd(bl.h, rocblas_evect_original, rocblas_fill_upper, Kc, HA.p, Kc, th_d.p, ework.p, info.p));
+    std::vector<double> th(Kc);
+    NM_HIP(hipMemcpyAsync(th.data(), th_d.p, 8 * Kc, hipMemcpyDeviceToHost, st));
+    NM_HIP(hipStreamSynchronize(st));
+    idx_sel.clear();
+    for (int i = 0; i < Kc; ++i)
+      if (th[i] >= a && th[i] <= b) idx_sel.push_back(i);
+    const int ns = (int)idx_sel.size();
+    th_sel.assign(ns, 0.0);
+    res_sel.assign(ns, 0.0);
+    bool res_ok = ns > 0;
+    if (ns > 0) {
+      // eigenvectors of the selected Ritz values are contiguous (ascending)
+      const double* Y = HA.p + (size_t)idx_sel[0] * Kc;
+      DBuf<double> X((size_t)n * ns), AX((size_t)n * ns), MX((size_t)n * ns), th_dev(ns), rn(ns), mn(ns);
+      bl.nn(n, Kc, ns, 1.0, V.p, Kmax, Y, Kc, 0.0, X.p, ns);
+      bl.nn(n, Kc, ns, 1.0, AV.p, Kmax, Y, Kc, 0.0, AX.p, ns);
+      mprod(X.p, MX.p, ns);
+      for (int i = 0; i < ns; ++i) th_sel[i] = th[idx_sel[i]];
+      NM_HIP(hipMemcpyAsync(th_dev.p, th_sel.data(), 8 * ns, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n * ns)), dim3(256), 0, st, n, ns, AX.p, MX.p, th_dev.p,
+                         AX.p);
+      col_dots(n, ns, AX.p, ns, AX.p, ns, rn.p, st);
+      col_dots(n, ns, MX.p, ns, MX.p, ns, mn.p, st);
+      std::vector<double> r2(ns), m2(ns);
+      NM_HIP(hipMemcpy(r2.data(), rn.p, 8 * ns, hipMemcpyDeviceToHost));
+      NM_HIP(hipMemcpy(m2.data(), mn.p, 8 * ns, hipMemcpyDeviceToHost));
+      for (int i = 0; i < ns; ++i) {
+        res_sel[i] = std::sqrt(r2[i]) / (std::fabs(th_sel[i]) * std::sqrt(m2[i]));
+        if (!(res_sel[i] <= tol)) res_ok = false;
+      }
+    }
+    // Ritz values of p(B) on the filtered part of the basis and their residual estimates
+    bool mu_ok = true;
+    int nbig = 0;
+    {
+      const int Kf = K - bs;  // columns whose images are in the basis
+      std::vector<double> Hs((size_t)Kf * Kf), w, S;
+      for (int q = 0; q < Kf; ++q)
+        for (int i = 0; i < Kf; ++i)
+          Hs[i + (size_t)q * Kf] = 0.5 * (H[(size_t)i + (size_t)q * Kmax] + H[(size_t)q + (size_t)i * Kmax]);
+      if (Kf <= 400) {
+        jacobi_eig(Kf, Hs, w, &S);
+      } else {
+        DBuf<double> hd((size_t)Kf * Kf), wd(Kf), ed(Kf);
+        NM_HIP(hipMemcpyAsync(hd.p, Hs.data(), 8 * Hs.size(), hipMemcpyHostToDevice, st));
+        NM_BLAS(rocsolver_dsyevd(bl.h, rocblas_evect_original, rocblas_fill_upper, Kf, hd.p, Kf, wd.p, ed.p, info.p));
+        w.resize(Kf);
+        S.resize((size_t)Kf * Kf);
+        NM_HIP(hipMemcpyAsync(w.data(), wd.p, 8 * Kf, hipMemcpyDeviceToHost, st));
+        NM_HIP(hipMemcpyAsync(S.data(), hd.p, 8 * S.size(), hipMemcpyDeviceToHost, st));
+        NM_HIP(hipStreamSynchronize(st));
+      }
+      double wmax = 0;
+      for (double x : w) wmax = std::max(wmax, std::fabs(x));
+      for (int i = 0; i < Kf; ++i) {
+        if (w[i] < tau) continue;
+        ++nbig;
+        // residual estimate || H[K-bs:K, Kf-bs:Kf] s_i[Kf-bs:Kf] ||
+        double r2 = 0;
+        for (int p = 0; p < bs; ++p) {
+          double s = 0;
+          for (int q = 0; q < bs; ++q)
+            s += H[(size_t)(Kf + p) + (size_t)(Kf - bs + q) * Kmax] * S[(size_t)(Kf - bs + q) + (size_t)i * Kf];
+          r2 += s * s;
+        }
+        if (std::sqrt(r2) > 1e-8 * wmax) mu_ok = false;
+      }
+    }
+    if (o.verbose)
+      fprintf(stderr, "[nmodes] block %d basis %d window-pairs %d resid-max %.2e big-mu %d mu-ok %d t=%.2fs\n", j, K,
+              ns, ns ? *std::max_element(res_sel.begin(), res_sel.end()) : 0.0, nbig, (int)mu_ok, clock.s());
+    bool stable = ns == last_count;
+    last_count = ns;
+    Kc_last = Kc;
+    Ysel.assign((size_t)Kc * std::max(ns, 0), 0.0);
+    if (ns) NM_HIP(hipMemcpy(Ysel.data(), HA.p + (size_t)idx_sel[0] * Kc, 8 * Ysel.size(), hipMemcpyDeviceToHost));
+    if (res_ok && stable && mu_ok) {
+      converged = true;
+      break;
+    }
+    if (K + bs > Kmax) break;
+  }
+
+  // ---------------- result: the min(nev, count) smallest pairs in the window
+  const int ns = (int)th_sel.size();
+  const int cnt = std::min(nev, ns);
+  int nconv = 0;
+  for (int i = 0; i < cnt; ++i) nconv += res_sel[i] <= tol;
+  nm_eig_result* r = new nm_eig_result();
+  memset(r, 0, sizeof(*r));
+  r->count = cnt;
+  r->n = n;
+  r->lambda = (double*)std::malloc(8 * std::max(cnt, 1));
+  r->resid = (double*)std::malloc(8 * std::max(cnt, 1));
+  for (int i = 0; i < cnt; ++i) {
+    r->lambda[i] = th_sel[i];
+    r->resid[i] = res_sel[i];
+  }
+  if (cnt > 0) {
+    DBuf<double> Yd((size_t)Kc_last * cnt), sg(cnt);
+    NM_HIP(hipMemcpyAsync(Yd.p, Ysel.data(), 8 * (size_t)Kc_last * cnt, hipMemcpyHostToDevice, st));
+    NM_HIP(hipMalloc((void**)&r->X, 8 * (size_t)n * cnt));
+    // Ritz vectors in the internal node order, then to the canonical order
+    DBuf<double> Xi((size_t)n * cnt);
+    bl.nn(n, Kc_last, cnt, 1.0, V.p, Kmax, Yd.p, Kc_last, 0.0, Xi.p, cnt);
+    permute_rows(N, 3 * cnt, Xi.p, r->X, P->perm.p, 8, st);
+    hipLaunchKernelGGL(k_col_sign, dim3(cnt), dim3(256), 0, st, n, cnt, r->X, sg.p);
+    hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(n * cnt)), dim3(256), 0, st, n, cnt, sg.p, r->X);
+  }
+  NM_HIP(hipStreamSynchronize(st));
+  r->degree = m;
+  r->kM = cfg.kM;
+  r->kP = cfg.kP;
+  r->block = bs;
+  r->basis = K;
+  r->bapps = bapps;
+  r->lmin = lmin;
+  r->lmax = lmax;
+  r->bytes = bytes;
+  r->filter_seconds = filter_time;
+  prof.harvest();
+  r->hot_launches = prof.launches;
+  r->hot_samples = prof.samples;
+  r->hot_ms = prof.samples ? prof.ms / prof.samples : 0.0;
+  {
+    const double sz = prec ? 4.0 : 8.0;
+    r->hot_bytes = (double)P->nnzb * (4.0 + sz) + 4.0 * (P->N + 1) + sz * P->N + 4.0 * n * bs * sz;
+  }
+  r->seconds = clock.s();
+  *out = r;
+  if (!converged || nconv < cnt) throw Error(NM_PARTIAL, "solve did not converge all pairs in the window");
+}
+
+}  // namespace nm

@@ -1,0 +1,210 @@
+// Internal declarations of the nmodes GPU library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/nmodes.h"
+
+namespace nm {
+
+struct Error : std::runtime_error {
+  nm_status code;
+  Error(nm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_error(const std::string& m);
+
+#define NM_HIP(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::nm::Error(NM_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+#define NM_BLAS(x)                                                                      \
+  do {                                                                                  \
+    rocblas_status s_ = (x);                                                            \
+    if (s_ != rocblas_status_success)                                                   \
+      throw ::nm::Error(NM_EDEVICE, std::string(#x) + ": rocblas status " +             \
+                                        std::to_string((int)s_));                       \
+  } while (0)
+#define NM_REQUIRE(cond, code, msg)                                                     \
+  do {                                                                                  \
+    if (!(cond)) throw ::nm::Error(code, msg);                                          \
+  } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  explicit DBuf(size_t count) { alloc(count); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) {
+      hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        n = 0;
+        throw Error(NM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      }
+    }
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// Reference-element tables (Appendix A): nodal Lagrange bases on the
+// reference tetrahedron I = {r_i >= -1, r1+r2+r3 <= -1} and triangle.
+struct RefTables {
+  int nd, npp, nfd, nfp;          // nodes: disp/pres on tet, disp/pres on face
+  double MM[10][10];              // mass  int_I l_a l_b
+  double KR[3][3][10][10];        // (D_j^T M D_l)_{ab}
+  double DR[3][10][10];           // (D_j^T M)_{ac}
+  double Mp[10][10];              // pressure mass
+  double Mfp[10][10];             // mixed mass int l^f_a l^p_c
+  double QP[3][10][10];           // (M_fp D^p_l)_{ac} = int l^f_a d_l l^p_c
+  double M2[6][6];                // face mass (disp)
+  double M2sp[6][6];              // face mixed mass (disp x pres)
+  double m_lo, m_hi, p_lo, p_hi;  // element bounds of spec(D^{-1} M), spec(D^{-1} K_p)
+};
+void build_ref_tables(int disp_order, int pres_order, RefTables& t);
+
+// Small dense symmetric eigensolver (cyclic Jacobi), host, column-major a[n*n].
+void jacobi_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>* v);
+
+}  // namespace nm
+
+// The pencil: device-resident matrices and numbering.
+struct nm_pencil {
+  int device = 0;
+  int disp_order = 1, pres_order = 1, nd = 4, npp = 4;
+  int64_t V = 0, T = 0, n_geom = 0, N = 0, n_solid = 0, n_pres = 0;
+  int64_t nnzb = 0, nnz_kp = 0, nnzb_eg = 0, n_fs = 0;
+  double omega[3] = {0, 0, 0};
+  bool gravity = false;
+  nm::RefTables ref;
+  // node graph (shared by A_G, M_s, R)
+  nm::DBuf<int32_t> row_ptr, col;
+  nm::DBuf<double> ag, ms, mdinv;  // ag [nnzb][9], ms [nnzb], mdinv [N] = 1/diag(M_s)
+  // pressure graph
+  nm::DBuf<int32_t> kp_ptr, kp_col;
+  nm::DBuf<double> kp, kpdinv;
+  // E_G by displacement node rows and its transpose by pressure rows, 3-vectors
+  nm::DBuf<int32_t> eg_ptr, eg_col, egt_ptr, egt_col;
+  nm::DBuf<double> eg_val, egt_val;
+  // FP32 shadows (built on first use)
+  nm::DBuf<float> ag32, ms32, mdinv32, kp32, kpdinv32, eg_val32, egt_val32;
+  // numbering (device): canonical node -> geometric node; canonical <-> internal
+  // (Morton) order of the displacement nodes: internal = perm[canonical],
+  // canonical = iperm[internal]
+  nm::DBuf<int32_t> node_geom, pres_geom, perm, iperm;
+  rocblas_handle blas = nullptr;
+  void ensure_fp32(hipStream_t st);
+};
+
+namespace nm {
+// pattern + assembly (nm_assemble.hip)
+void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStream_t st);
+
+// operators (nm_ops.hip)
+// Sampled HIP-event timing of the hot kernel (a middle Chebyshev-Jacobi
+// step of the M solve): one launch in `every` is bracketed by events on
+// its own stream; harvest() adds the elapsed times once the stream passed.
+struct KernelProf {
+  int every = 32;
+  int64_t launches = 0, samples = 0;
+  double ms = 0.0;
+  std::vector<hipEvent_t> pool;  // pairs (start, stop)
+  int used = 0;
+  void before(hipStream_t st, bool& sampled);
+  void after(hipStream_t st);
+  void harvest();
+  ~KernelProf();
+};
+
+struct ApplyCfg {
+  int kM = 0, kP = 0;
+  int precision = 0;
+  KernelProf* prof = nullptr;
+};
+int cheb_steps(double lo, double hi, double tol);
+// operators on vectors in the internal node order
+void apply_op(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg,
+              hipStream_t st);
+// the same on vectors in the canonical node order (C ABI)
+void api_apply(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg,
+               hipStream_t st);
+// dst[r] = src[map[r]] for rows of w elements (8 or 4 bytes each)
+void permute_rows(int64_t rows, int w, const void* src, void* dst, const int32_t* map, int elem_bytes,
+                  hipStream_t st);
+
+// workspace for filter applications on a block of ncols columns
+template <class T>
+struct FilterWork {
+  int b = 0;
+  DBuf<T> x0, w0, w1, f, ya, yb, pt, ps, pa, pb;
+  void ensure(const nm_pencil* P, int ncols);
+};
+template <class T>
+void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0,
+                  double s0, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
+                  hipStream_t st);
+template <class T>
+void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
+             hipStream_t st);
+
+// column dot products out[v] = sum_r X[r*ldx+v] Y[r*ldy+v] (deterministic)
+void col_dots(int64_t rows, int ncols, const double* X, int ldx, const double* Y, int ldy,
+              double* out_dev, hipStream_t st);
+void convert_f64_f32(int64_t n, const double* a, float* b, hipStream_t st);
+void convert_f32_f64(int64_t n, const float* a, double* b, hipStream_t st);
+
+// filter design (nm_eig.hip)
+void jackson_chebyshev(double a, double b, double lmin, double lmax, int m, double* mu);
+int choose_degree(double a, double b, double lmin, double lmax, double guard, int mode);
+double cheb_eval(const double* mu, int m, double t);
+
+void spectrum_bounds(const nm_pencil* P, int steps, uint64_t seed, hipStream_t st, double* lmin, double* lmax);
+void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
+                  nm_eig_result** out);
+void project_rotation(const nm_pencil* P, const nm_eig_result* basis, double a, double b,
+                      hipStream_t st, nm_rot_result** out);
+
+// launch geometry: grid padded to a multiple of 8 workgroups so that the
+// XCD-aware remap in the kernels is a bijection
+inline unsigned grid_for(int64_t threads, int block = 256) {
+  int64_t g = (threads + block - 1) / block;
+  g = (g + 7) / 8 * 8;
+  if (g < 8) g = 8;
+  return (unsigned)g;
+}
+}  // namespace nm
+
+// Workgroups are dispatched round-robin over the 8 XCDs (blockIdx % 8).
+// Remap so that each XCD works on one contiguous eighth of the index range:
+// neighbouring rows share vector gathers through that XCD's L2.
+__device__ __forceinline__ int64_t nm_xcd_block() {
+  const unsigned per = gridDim.x >> 3;
+  return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}

@@ -1,0 +1,839 @@
+// Sparse operators of the pencil and the polynomial filter on the device.
+//
+// The paper accesses A, M and M^{-1} only through matrix-vector products
+// (Sec. 6.1); most of the work of the eigensolver is here.  Every kernel
+// is bound by HBM bandwidth: vectors are blocks [rows][w] with the w = 3b
+// entries of a displacement node (components x columns) contiguous, so a
+// gather of a neighbour row is one contiguous 3b-element segment, a
+// lane handles one (row, entry) pair and the CSR indices and values of a
+// row are loaded once per row group and broadcast.
+//
+// M^{-1} and K_p^{-1}: Chebyshev iteration preconditioned by the diagonal,
+// on the element bounds [lo, hi] of spec(D^{-1} M), written on iterates:
+//   y_1 = D^{-1} f / theta,
+//   y_{j+1} = y_j + rho_j rho_{j-1} (y_j - y_{j-1}) + (2 rho_j / delta) D^{-1} (f - M y_j),
+//   rho_0 = delta/theta, rho_j = 1 / (2 theta/delta - rho_{j-1}).
+// The last step of the M solve is fused with the three-term Chebyshev
+// filter update (W_{k+1} = a1 (B W_k - c W_k) + a2 W_{k-1}, Y += mu W_{k+1}).
+#include <cmath>
+#include <type_traits>
+
+#include "nm_internal.h"
+
+namespace nm {
+namespace {
+
+__device__ __forceinline__ int64_t gtid() { return nm_xcd_block() * blockDim.x + threadIdx.x; }
+
+// ---- vector access: V consecutive elements of a row as one 8/16-byte load
+template <class T, int V>
+struct Vx {
+  T v[V];
+};
+template <class T, int V>
+__device__ __forceinline__ Vx<T, V> ldv(const T* __restrict__ p) {
+  Vx<T, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = *p;
+  } else if constexpr (std::is_same<T, double>::value && V == 2) {
+    double2 q = *reinterpret_cast<const double2*>(p);
+    r.v[0] = q.x; r.v[1] = q.y;
+  } else if constexpr (std::is_same<T, float>::value && V == 2) {
+    float2 q = *reinterpret_cast<const float2*>(p);
+    r.v[0] = q.x; r.v[1] = q.y;
+  } else {
+    float4 q = *reinterpret_cast<const float4*>(p);
+    r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+  }
+  return r;
+}
+template <class T, int V>
+__device__ __forceinline__ void stv(T* __restrict__ p, const Vx<T, V>& r) {
+  if constexpr (V == 1) {
+    *p = r.v[0];
+  } else if constexpr (std::is_same<T, double>::value && V == 2) {
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+  } else if constexpr (std::is_same<T, float>::value && V == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(r.v[0], r.v[1]);
+  } else {
+    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  }
+}
+
+// LDS staging of the CSR entries of the rows a workgroup touches: the
+// workgroup's lanes cover rows [r0, r1]; their column indices and values
+// are loaded cooperatively (coalesced) into LDS, so that each lane can then
+// issue all gathers of its row back to back instead of a dependent
+// index-load -> gather chain per nonzero.
+constexpr int STAGE_CAP = 2048;
+template <class T, int NV>
+struct Stage {
+  int32_t kbeg;
+  bool ok;
+};
+template <class T, int NV>
+__device__ __forceinline__ Stage<T, NV> stage_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const T* __restrict__ val, uint32_t rows, uint32_t wl,
+                                                  int32_t* s_col, T* s_val) {
+  const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
+  const uint32_t r0 = min(g0 / wl, rows - 1);
+  const uint32_t r1 = min((g0 + blockDim.x - 1) / wl, rows - 1);
+  const int32_t kb = rp[r0], ke = rp[r1 + 1];
+  Stage<T, NV> st{kb, (ke - kb) <= STAGE_CAP};
+  if (st.ok) {
+    for (int32_t i = threadIdx.x; i < ke - kb; i += blockDim.x) {
+      s_col[i] = col[kb + i];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) s_val[NV * i + q] = val[(size_t)NV * (kb + i) + q];
+    }
+  }
+  __syncthreads();
+  return st;
+}
+
+// sum_k val[k] X[col[k] * w + e .. e + V) over the row's entries, from LDS
+// (or global memory when the rows did not fit): 8 gathers in flight per lane
+// cl / vl point at the first staged entry (entry index `base`) or at the
+// global arrays (base 0); entries are read at cl[k - base], so no pointer
+// outside an allocation is ever formed.
+template <class T, int V>
+__device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int32_t base, int32_t k0, int32_t k1,
+                                             const T* __restrict__ X, uint32_t w, uint32_t e) {
+  Vx<T, V> acc;
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+  for (int32_t k = k0; k < k1; k += 8) {
+    uint32_t c[8];
+    T a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = k + u < k1;
+      const int32_t kk = (in ? k + u : k0) - base;
+      c[u] = (uint32_t)cl[kk];
+      a[u] = in ? vl[kk] : T(0);
+    }
+    Vx<T, V> x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc.v[i] += a[u] * x[u].v[i];
+  }
+  return acc;
+}
+
+// flat index of this lane in a launch covering rows * (w / V) lanes
+__device__ __forceinline__ uint32_t lane_id() { return (uint32_t)nm_xcd_block() * blockDim.x + threadIdx.x; }
+
+// F = A_G X [+ E_G S] ; optionally Y1 = D^{-1} F / theta (first Chebyshev iterate).
+// Lane (row, c, column group of V): 3 block entries and 3 gathered V-vectors per nonzero block.
+template <class T, int V>
+__global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const T* __restrict__ ag,
+                                                  const T* __restrict__ X, const int32_t* __restrict__ egp,
+                                                  const int32_t* __restrict__ egc, const T* __restrict__ egv,
+                                                  const T* __restrict__ S, T* __restrict__ F,
+                                                  const T* __restrict__ dinv, T inv_theta, T* __restrict__ Y1) {
+  constexpr int CAP = STAGE_CAP / 4;
+  __shared__ int32_t s_col[CAP];
+  __shared__ T s_val[9 * CAP];
+  const uint32_t w = 3 * b, wl = w / V;
+  const uint32_t g = lane_id();
+  const bool active = g < N * wl;
+  // stage (indices and 3x3 blocks) of this workgroup's rows
+  const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
+  const uint32_t r0 = min(g0 / wl, N - 1), r1 = min((g0 + blockDim.x - 1) / wl, N - 1);
+  const int32_t kb = rp[r0], ke = rp[r1 + 1];
+  const bool staged = ke - kb <= CAP;
+  if (staged) {
+    for (int32_t i = threadIdx.x; i < ke - kb; i += blockDim.x) s_col[i] = col[kb + i];
+    for (int32_t i = threadIdx.x; i < 9 * (ke - kb); i += blockDim.x) s_val[i] = ag[9 * (size_t)kb + i];
+  }
+  __syncthreads();
+  if (!active) return;
+  const uint32_t row = g / wl;
+  const uint32_t e = (g - row * wl) * V;
+  const uint32_t c = e / b, v = e - c * b;
+  const int32_t* cl = staged ? s_col : col;
+  const T* vl = staged ? s_val : ag;
+  const int32_t base = staged ? kb : 0;
+  Vx<T, V> acc;
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+  const int32_t k0 = rp[row], k1 = rp[row + 1];
+  for (int32_t k = k0; k < k1; k += 4) {
+    uint32_t cc[4];
+    T a[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = k + u < k1;
+      const int32_t kk = (in ? k + u : k0) - base;
+      cc[u] = (uint32_t)cl[kk];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a[u][d] = in ? vl[9 * (size_t)kk + 3 * c + d] : T(0);
+    }
+    Vx<T, V> x[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[u][d] = ldv<T, V>(X + (size_t)(cc[u] * w + d * b + v));
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] += a[u][d] * x[u][d].v[i];
+  }
+  if (S) {
+    for (int32_t q = egp[row]; q < egp[row + 1]; ++q) {
+      const T ev = egv[3 * (size_t)q + c];
+      Vx<T, V> s = ldv<T, V>(S + (size_t)((uint32_t)egc[q] * b + v));
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc.v[i] += ev * s.v[i];
+    }
+  }
+  const size_t o = (size_t)row * w + e;
+  if (F) stv<T, V>(F + o, acc);
+  if (Y1) {
+    const T sc = dinv[row] * inv_theta;
+    Vx<T, V> y;
+#pragma unroll
+    for (int i = 0; i < V; ++i) y.v[i] = sc * acc.v[i];
+    stv<T, V>(Y1 + o, y);
+  }
+}
+
+// T_p = E_G^T X  (pressure rows, b entries)
+template <class T>
+__global__ __launch_bounds__(256) void k_egt(int64_t NP, int b, const int32_t* __restrict__ p,
+                                             const int32_t* __restrict__ c, const T* __restrict__ val,
+                                             const T* __restrict__ X, T* __restrict__ out) {
+  int64_t g = gtid();
+  if (g >= NP * b) return;
+  int64_t row = g / b;
+  int v = (int)(g - row * b);
+  const int w = 3 * b;
+  T acc = 0;
+  for (int32_t k = p[row]; k < p[row + 1]; ++k) {
+    const T* x = X + (int64_t)c[k] * w + v;
+    const T* e = val + 3 * (int64_t)k;
+    acc += e[0] * x[0] + e[1] * x[b] + e[2] * x[2 * b];
+  }
+  out[g] = acc;
+}
+
+// Y = E_G S (displacement rows)
+template <class T>
+__global__ __launch_bounds__(256) void k_eg(int64_t N, int b, const int32_t* __restrict__ p,
+                                            const int32_t* __restrict__ c, const T* __restrict__ val,
+                                            const T* __restrict__ S, T* __restrict__ Y) {
+  const int w = 3 * b;
+  int64_t g = gtid();
+  if (g >= N * w) return;
+  int64_t row = g / w;
+  int e = (int)(g - row * w);
+  int cc = e / b, v = e - cc * b;
+  T acc = 0;
+  for (int32_t k = p[row]; k < p[row + 1]; ++k) acc += val[3 * (int64_t)k + cc] * S[(int64_t)c[k] * b + v];
+  Y[g] = acc;
+}
+
+// Y = (S (x) I_w) X for a scalar CSR S and row width w
+template <class T, int V>
+__global__ __launch_bounds__(256) void k_spmm_scalar(uint32_t rows, uint32_t w, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                     const T* __restrict__ X, T* __restrict__ Y) {
+  __shared__ int32_t s_col[STAGE_CAP];
+  __shared__ T s_val[STAGE_CAP];
+  const uint32_t wl = w / V;
+  const uint32_t g = lane_id();
+  auto sg = stage_rows<T, 1>(rp, col, val, rows, wl, s_col, s_val);
+  if (g >= rows * wl) return;
+  const uint32_t row = g / wl, e = (g - row * wl) * V;
+  const int32_t* cl = sg.ok ? s_col : col;
+  const T* vl = sg.ok ? s_val : val;
+  Vx<T, V> acc = row_spmv<T, V>(cl, vl, sg.ok ? sg.kbeg : 0, rp[row], rp[row + 1], X, w, e);
+  stv<T, V>(Y + (size_t)row * w + e, acc);
+}
+
+// Y = (M_s (x) [Omega]_x) X
+template <class T>
+__global__ __launch_bounds__(256) void k_spmm_coriolis(int64_t N, int b, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col, const T* __restrict__ ms,
+                                                       T o0, T o1, T o2, const T* __restrict__ X, T* __restrict__ Y) {
+  const int w = 3 * b;
+  int64_t g = gtid();
+  if (g >= N * w) return;
+  int64_t row = g / w;
+  int e = (int)(g - row * w);
+  int c = e / b, v = e - c * b;
+  T s0 = 0, s1 = 0, s2 = 0;
+  for (int32_t k = rp[row]; k < rp[row + 1]; ++k) {
+    const T m = ms[k];
+    const T* x = X + (int64_t)col[k] * w + v;
+    s0 += m * x[0];
+    s1 += m * x[b];
+    s2 += m * x[2 * b];
+  }
+  // (Omega x s)_c
+  T r = c == 0 ? (o1 * s2 - o2 * s1) : (c == 1 ? (o2 * s0 - o0 * s2) : (o0 * s1 - o1 * s0));
+  Y[g] = r;
+}
+
+template <class T, int V>
+__global__ __launch_bounds__(256) void k_cj_first(uint32_t rows, uint32_t w, const T* __restrict__ dinv,
+                                                  const T* __restrict__ f, T inv_theta, T* __restrict__ y) {
+  const uint32_t wl = w / V;
+  const uint32_t g = lane_id();
+  if (g >= rows * wl) return;
+  const uint32_t row = g / wl, e = (g - row * wl) * V;
+  const size_t o = (size_t)row * w + e;
+  Vx<T, V> x = ldv<T, V>(f + o);
+  const T sc = dinv[row] * inv_theta;
+#pragma unroll
+  for (int i = 0; i < V; ++i) x.v[i] *= sc;
+  stv<T, V>(y + o, x);
+}
+
+// One Chebyshev-Jacobi step.  mode 0: out = y_{j+1}.  mode 1: filter update
+// with z = y_{j+1}:  wout = a1 (z - cs win) + a2 wprev;
+// ymode 1: Yacc = mu0 win + mu wout; ymode 2: Yacc += mu wout.
+// out may alias yprev (same element read then written by one lane), wout
+// may alias wprev.
+template <class T, int V>
+__global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                 const T* __restrict__ dinv, const T* __restrict__ f,
+                                                 const T* __restrict__ ycur, const T* yprev, T alpha, T beta,
+                                                 int prev_zero, int mode, T* out, const T* __restrict__ win,
+                                                 const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, T* wout,
+                                                 T* Yacc) {
+  __shared__ int32_t s_col[STAGE_CAP];
+  __shared__ T s_val[STAGE_CAP];
+  const uint32_t wl = w / V;
+  const uint32_t g = lane_id();
+  auto sg = stage_rows<T, 1>(rp, col, val, rows, wl, s_col, s_val);
+  if (g >= rows * wl) return;
+  const uint32_t row = g / wl, e = (g - row * wl) * V;
+  const size_t o = (size_t)row * w + e;
+  // own-row operands first, so their latency overlaps the gathers
+  const Vx<T, V> yc = ldv<T, V>(ycur + o);
+  const Vx<T, V> ff = ldv<T, V>(f + o);
+  Vx<T, V> yp;
+  if (prev_zero) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) yp.v[i] = T(0);
+  } else {
+    yp = ldv<T, V>(yprev + o);
+  }
+  const T dr = dinv[row];
+  const int32_t* cl = sg.ok ? s_col : col;
+  const T* vl = sg.ok ? s_val : val;
+  Vx<T, V> s = row_spmv<T, V>(cl, vl, sg.ok ? sg.kbeg : 0, rp[row], rp[row + 1], ycur, w, e);
+  const T bd = beta * dr;
+  Vx<T, V> z;
+#pragma unroll
+  for (int i = 0; i < V; ++i) z.v[i] = yc.v[i] + alpha * (yc.v[i] - yp.v[i]) + bd * (ff.v[i] - s.v[i]);
+  if (mode == 0) {
+    stv<T, V>(out + o, z);
+    return;
+  }
+  const Vx<T, V> wi = ldv<T, V>(win + o);
+  Vx<T, V> wo;
+#pragma unroll
+  for (int i = 0; i < V; ++i) wo.v[i] = a1 * (z.v[i] - cs * wi.v[i]);
+  if (a2 != T(0)) {
+    const Vx<T, V> wp = ldv<T, V>(wprev + o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) wo.v[i] += a2 * wp.v[i];
+  }
+  stv<T, V>(wout + o, wo);
+  if (ymode == 1) {
+    Vx<T, V> yy;
+#pragma unroll
+    for (int i = 0; i < V; ++i) yy.v[i] = mu0 * wi.v[i] + mu * wo.v[i];
+    stv<T, V>(Yacc + o, yy);
+  } else if (ymode == 2) {
+    Vx<T, V> yy = ldv<T, V>(Yacc + o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) yy.v[i] += mu * wo.v[i];
+    stv<T, V>(Yacc + o, yy);
+  }
+}
+
+template <class T>
+__global__ void k_scale_copy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
+  int64_t g = gtid();
+  if (g < n) y[g] = a * x[g];
+}
+
+__global__ void k_f64_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  int64_t g = gtid();
+  if (g < n) b[g] = (float)a[g];
+}
+__global__ void k_f32_f64(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  int64_t g = gtid();
+  if (g < n) b[g] = (double)a[g];
+}
+
+// column dot products, stage 1: partial sums per workgroup (fixed order)
+__global__ __launch_bounds__(256) void k_coldot_partial(int64_t rows, int nc, const double* __restrict__ X, int ldx,
+                                                        const double* __restrict__ Y, int ldy, int64_t rows_per,
+                                                        double* __restrict__ part) {
+  // workgroup blockIdx.x handles rows [blk*rows_per, ...) for all nc columns
+  __shared__ double red[256];
+  int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = r0 + rows_per;
+  if (r1 > rows) r1 = rows;
+  for (int v = 0; v < nc; ++v) {
+    double s = 0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) s += X[r * ldx + v] * Y[r * ldy + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nc + v] = red[0];
+    __syncthreads();
+  }
+}
+__global__ void k_coldot_final(int nblk, int nc, const double* __restrict__ part, double* __restrict__ out) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nc) return;
+  double s = 0;
+  for (int i = 0; i < nblk; ++i) s += part[(int64_t)i * nc + v];
+  out[v] = s;
+}
+
+// ---- launch helpers: V = elements per lane (16-byte loads where the row
+// width allows), lanes = rows * (w / V)
+template <class T>
+int pick_v(uint32_t w) {
+  if (std::is_same<T, float>::value && w % 4 == 0) return 4;
+  return w % 2 == 0 ? 2 : 1;
+}
+#define NM_LAUNCH_V(KERN, T, V, lanes, st, ...)                                                         \
+  do {                                                                                                 \
+    if ((V) == 4)                                                                                      \
+      hipLaunchKernelGGL((KERN<T, 4>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);           \
+    else if ((V) == 2)                                                                                 \
+      hipLaunchKernelGGL((KERN<T, 2>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);           \
+    else                                                                                               \
+      hipLaunchKernelGGL((KERN<T, 1>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);           \
+  } while (0)
+
+template <class T>
+void launch_spmm_scalar(int64_t rows, int w, const int32_t* rp, const int32_t* col, const T* val, const T* X, T* Y,
+                        hipStream_t st) {
+  int v = pick_v<T>(w);
+  NM_LAUNCH_V(k_spmm_scalar, T, v, rows * (w / v), st, (uint32_t)rows, (uint32_t)w, rp, col, val, X, Y);
+}
+template <class T>
+void launch_cj_first(int64_t rows, int w, const T* dinv, const T* f, T inv_theta, T* y, hipStream_t st) {
+  int v = pick_v<T>(w);
+  NM_LAUNCH_V(k_cj_first, T, v, rows * (w / v), st, (uint32_t)rows, (uint32_t)w, dinv, f, inv_theta, y);
+}
+template <class T>
+void launch_cj_step(int64_t rows, int w, const int32_t* rp, const int32_t* col, const T* val, const T* dinv,
+                    const T* f, const T* ycur, const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out,
+                    const T* win, const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc,
+                    hipStream_t st) {
+  int v = pick_v<T>(w);
+  NM_LAUNCH_V(k_cj_step, T, v, rows * (w / v), st, (uint32_t)rows, (uint32_t)w, rp, col, val, dinv, f, ycur, yprev,
+              alpha, beta, prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, mu0, mu, wout, Yacc);
+}
+template <class T>
+void launch_apply_ag(int64_t N, int b, const int32_t* rp, const int32_t* col, const T* ag, const T* X,
+                     const int32_t* egp, const int32_t* egc, const T* egv, const T* S, T* F, const T* dinv,
+                     T inv_theta, T* Y1, hipStream_t st) {
+  int v = pick_v<T>(b);
+  NM_LAUNCH_V(k_apply_ag, T, v, N * (3 * b / v), st, (uint32_t)N, (uint32_t)b, rp, col, ag, X, egp, egc, egv, S, F,
+              dinv, inv_theta, Y1);
+}
+
+struct ChebCoef {
+  double theta, delta, sigma;
+  std::vector<double> alpha, beta;  // step j = 1..k-1
+};
+ChebCoef cheb_coef(double lo, double hi, int k) {
+  ChebCoef c;
+  c.theta = 0.5 * (hi + lo);
+  c.delta = 0.5 * (hi - lo);
+  c.sigma = c.theta / c.delta;
+  double rho_prev = 1.0 / c.sigma;
+  for (int j = 1; j < k; ++j) {
+    double rho = 1.0 / (2.0 * c.sigma - rho_prev);
+    c.alpha.push_back(rho * rho_prev);
+    c.beta.push_back(2.0 * rho / c.delta);
+    rho_prev = rho;
+  }
+  return c;
+}
+
+template <class T>
+struct Mats {
+  const T *ag, *ms, *mdinv, *kp, *kpdinv, *eg, *egt;
+};
+template <class T>
+Mats<T> mats(const nm_pencil* P);
+template <>
+Mats<double> mats<double>(const nm_pencil* P) {
+  return {P->ag.p, P->ms.p, P->mdinv.p, P->kp.p, P->kpdinv.p, P->eg_val.p, P->egt_val.p};
+}
+template <>
+Mats<float> mats<float>(const nm_pencil* P) {
+  return {P->ag32.p, P->ms32.p, P->mdinv32.p, P->kp32.p, P->kpdinv32.p, P->eg_val32.p, P->egt_val32.p};
+}
+
+#define LAUNCH(kern, threads, st, ...) \
+  hipLaunchKernelGGL(kern, dim3(grid_for(threads)), dim3(256), 0, st, __VA_ARGS__)
+
+// S_p(t): fixed-k Chebyshev-Jacobi solve with K_p; result pointer returned
+template <class T>
+T* kp_solve(const nm_pencil* P, int b, const T* t, int kP, T* pa, T* pb, hipStream_t st) {
+  auto m = mats<T>(P);
+  const int64_t NP = P->n_pres;
+  ChebCoef cc = cheb_coef(P->ref.p_lo, P->ref.p_hi, kP);
+  launch_cj_first<T>(NP, b, m.kpdinv, t, (T)(1.0 / cc.theta), pa, st);
+  T *cur = pa, *prev = pb;
+  for (int j = 1; j < kP; ++j) {
+    launch_cj_step<T>(NP, b, P->kp_ptr.p, P->kp_col.p, m.kp, m.kpdinv, t, cur, prev, (T)cc.alpha[j - 1],
+                      (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, prev, nullptr, nullptr, T(0), T(0), T(0), 0, T(0), T(0),
+                      nullptr, nullptr, st);
+    std::swap(cur, prev);
+  }
+  return cur;
+}
+
+// F = A X (Cowling operator) and optionally Y1 = D^{-1} F / theta
+template <class T>
+void a_apply(const nm_pencil* P, int b, const T* X, T* F, T* Y1, double inv_theta, int kP, FilterWork<T>& w,
+             hipStream_t st) {
+  auto m = mats<T>(P);
+  const T* S = nullptr;
+  if (P->n_pres > 0) {
+    LAUNCH(k_egt<T>, P->n_pres * b, st, P->n_pres, b, P->egt_ptr.p, P->egt_col.p, m.egt, X, w.pt.p);
+    S = kp_solve<T>(P, b, w.pt.p, kP, w.pa.p, w.pb.p, st);
+  }
+  launch_apply_ag<T>(P->N, b, P->row_ptr.p, P->col.p, m.ag, X, P->eg_ptr.p, P->eg_col.p, m.eg, S, F, m.mdinv,
+                     (T)inv_theta, Y1, st);
+}
+
+struct Update {
+  bool on = false;
+  const void* win = nullptr;
+  const void* wprev = nullptr;
+  double a1 = 0, cs = 0, a2 = 0, mu0 = 0, mu = 0;
+  int ymode = 0;
+  void* wout = nullptr;
+  void* Y = nullptr;
+};
+
+// z = S_M(A X); either written to Z or consumed by the filter update u
+template <class T>
+void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, int kM, int kP, FilterWork<T>& w,
+                  hipStream_t st, KernelProf* prof = nullptr) {
+  NM_REQUIRE(kM >= 2, NM_EINVAL, "the M solve needs at least 2 Chebyshev steps");
+  auto m = mats<T>(P);
+  ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, kM);
+  a_apply<T>(P, b, X, w.f.p, w.ya.p, 1.0 / cc.theta, kP, w, st);
+  const int64_t N = P->N;
+  const int wd = 3 * b;
+  T *cur = w.ya.p, *prev = w.yb.p;
+  for (int j = 1; j < kM; ++j) {
+    bool last = j == kM - 1;
+    if (!last) {
+      bool sampled = false;
+      if (prof && j >= 2) prof->before(st, sampled);
+      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
+                        (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, prev, nullptr, nullptr, T(0), T(0), T(0), 0, T(0),
+                        T(0), nullptr, nullptr, st);
+      if (sampled) prof->after(st);
+      std::swap(cur, prev);
+    } else if (!u.on) {
+      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
+                        (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, Z, nullptr, nullptr, T(0), T(0), T(0), 0, T(0), T(0),
+                        nullptr, nullptr, st);
+    } else {
+      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
+                        (T)cc.beta[j - 1], j == 1 ? 1 : 0, 1, nullptr, (const T*)u.win, (const T*)u.wprev, (T)u.a1,
+                        (T)u.cs, (T)u.a2, u.ymode, (T)u.mu0, (T)u.mu, (T*)u.wout, (T*)u.Y, st);
+    }
+  }
+}
+
+}  // namespace
+
+int cheb_steps(double lo, double hi, double tol) {
+  double kap = hi / lo;
+  double r = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
+  int k = (int)std::ceil(std::log(2.0 / tol) / std::log(1.0 / r));
+  return std::max(k, 2);
+}
+
+template <class T>
+void FilterWork<T>::ensure(const nm_pencil* P, int ncols) {
+  if (b == ncols && f.p) return;
+  b = ncols;
+  size_t n = (size_t)P->N * 3 * ncols, np = (size_t)std::max<int64_t>(P->n_pres, 1) * ncols;
+  x0.alloc(n); w0.alloc(n); w1.alloc(n); f.alloc(n); ya.alloc(n); yb.alloc(n);
+  pt.alloc(np); ps.alloc(np); pa.alloc(np); pb.alloc(np);
+}
+
+template <class T>
+void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
+             hipStream_t st) {
+  w.ensure(P, ncols);
+  b_apply_impl<T>(P, ncols, X, Y, Update{}, cfg.kM, cfg.kP, w, st);
+}
+
+// Y = p(B) X, or ((B - l0)/s0) p(B) X when s0 != 0; p = sum_k mu_k T_k((t - c)/e)
+template <class T>
+void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0, double s0, int ncols,
+                  const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w, hipStream_t st) {
+  w.ensure(P, ncols);
+  const int64_t n = P->N * 3 * ncols;
+  if (m == 0 && s0 == 0.0) {
+    LAUNCH(k_scale_copy<T>, n, st, n, (T)mu[0], X, Y);
+    return;
+  }
+  T* bufs[2] = {w.w0.p, w.w1.p};
+  const T* win = X;
+  int nb = 0;  // next free buffer
+  if (s0 != 0.0) {
+    Update u;
+    u.on = true; u.win = X; u.a1 = 1.0 / s0; u.cs = l0; u.a2 = 0.0; u.ymode = 0; u.wout = bufs[0];
+    b_apply_impl<T>(P, ncols, X, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
+    win = bufs[0];
+    nb = 1;
+    if (m == 0) {
+      LAUNCH(k_scale_copy<T>, n, st, n, (T)mu[0], win, Y);
+      return;
+    }
+  }
+  // step 1: W1 = (B W0 - c W0)/e ; Y = mu0 W0 + mu1 W1
+  const T* wprev = nullptr;
+  {
+    Update u;
+    u.on = true; u.win = win; u.a1 = 1.0 / e; u.cs = c; u.a2 = 0.0; u.ymode = 1; u.mu0 = mu[0]; u.mu = mu[1];
+    u.wout = bufs[nb]; u.Y = Y;
+    b_apply_impl<T>(P, ncols, win, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
+    wprev = win;
+    win = bufs[nb];
+    nb ^= 1;
+  }
+  for (int k = 2; k <= m; ++k) {
+    // output buffer: the one holding wprev if it is a work buffer, else the free one
+    T* out = (wprev == bufs[0] || wprev == bufs[1]) ? (T*)wprev : bufs[nb];
+    Update u;
+    u.on = true; u.win = win; u.wprev = wprev; u.a1 = 2.0 / e; u.cs = c; u.a2 = -1.0; u.ymode = 2; u.mu = mu[k];
+    u.wout = out; u.Y = Y;
+    b_apply_impl<T>(P, ncols, win, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
+    wprev = win;
+    win = out;
+    nb = (out == bufs[0]) ? 1 : 0;
+  }
+}
+
+template struct FilterWork<double>;
+template struct FilterWork<float>;
+template void b_apply<double>(const nm_pencil*, int, const double*, double*, const ApplyCfg&, FilterWork<double>&,
+                              hipStream_t);
+template void b_apply<float>(const nm_pencil*, int, const float*, float*, const ApplyCfg&, FilterWork<float>&,
+                             hipStream_t);
+template void filter_apply<double>(const nm_pencil*, const double*, int, double, double, double, double, int,
+                                   const double*, double*, const ApplyCfg&, FilterWork<double>&, hipStream_t);
+template void filter_apply<float>(const nm_pencil*, const double*, int, double, double, double, double, int,
+                                  const float*, float*, const ApplyCfg&, FilterWork<float>&, hipStream_t);
+
+template <class T>
+static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* Yv, const ApplyCfg& cfg,
+                       hipStream_t st) {
+  const T* X = (const T*)Xv;
+  T* Y = (T*)Yv;
+  auto m = mats<T>(P);
+  const int64_t N = P->N, NP = P->n_pres;
+  const int wd = 3 * b;
+  switch (op) {
+    case NM_OP_AG:
+      launch_apply_ag<T>(N, b, P->row_ptr.p, P->col.p, m.ag, X, nullptr, nullptr, nullptr, nullptr, Y, nullptr, T(0),
+                         nullptr, st);
+      break;
+    case NM_OP_M:
+      launch_spmm_scalar<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, X, Y, st);
+      break;
+    case NM_OP_R:
+      LAUNCH(k_spmm_coriolis<T>, N * wd, st, N, b, P->row_ptr.p, P->col.p, m.ms, (T)P->omega[0], (T)P->omega[1],
+             (T)P->omega[2], X, Y);
+      break;
+    case NM_OP_KP:
+      NM_REQUIRE(NP > 0, NM_EINVAL, "pencil has no pressure unknowns");
+      launch_spmm_scalar<T>(NP, b, P->kp_ptr.p, P->kp_col.p, m.kp, X, Y, st);
+      break;
+    case NM_OP_EG:
+      NM_REQUIRE(NP > 0, NM_EINVAL, "pencil has no pressure unknowns");
+      LAUNCH(k_eg<T>, N * wd, st, N, b, P->eg_ptr.p, P->eg_col.p, m.eg, X, Y);
+      break;
+    case NM_OP_EGT:
+      NM_REQUIRE(NP > 0, NM_EINVAL, "pencil has no pressure unknowns");
+      LAUNCH(k_egt<T>, NP * b, st, NP, b, P->egt_ptr.p, P->egt_col.p, m.egt, X, Y);
+      break;
+    case NM_OP_KPINV: {
+      NM_REQUIRE(NP > 0, NM_EINVAL, "pencil has no pressure unknowns");
+      DBuf<T> pa(NP * b), pb(NP * b);
+      T* r = kp_solve<T>(P, b, X, cfg.kP, pa.p, pb.p, st);
+      NM_HIP(hipMemcpyAsync(Y, r, NP * b * sizeof(T), hipMemcpyDeviceToDevice, st));
+      NM_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    case NM_OP_A: {
+      FilterWork<T> w;
+      w.ensure(P, b);
+      a_apply<T>(P, b, X, Y, nullptr, 0.0, cfg.kP, w, st);
+      NM_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    case NM_OP_MINV: {
+      NM_REQUIRE(cfg.kM >= 2, NM_EINVAL, "kM must be >= 2");
+      DBuf<T> ya(N * wd), yb(N * wd);
+      ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, cfg.kM);
+      launch_cj_first<T>(N, wd, m.mdinv, X, (T)(1.0 / cc.theta), ya.p, st);
+      T *cur = ya.p, *prev = yb.p;
+      for (int j = 1; j < cfg.kM; ++j) {
+        T* out = j == cfg.kM - 1 ? Y : prev;
+        launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, X, cur, prev, (T)cc.alpha[j - 1],
+                          (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, out, nullptr, nullptr, T(0), T(0), T(0), 0, T(0),
+                          T(0), nullptr, nullptr, st);
+        std::swap(cur, prev);
+      }
+      NM_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    case NM_OP_B: {
+      FilterWork<T> w;
+      b_apply<T>(P, b, X, Y, cfg, w, st);
+      NM_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    default:
+      throw Error(NM_EINVAL, "unknown operator " + std::to_string(op));
+  }
+  NM_HIP(hipGetLastError());
+}
+
+template <class T>
+__global__ void k_permute_rows(int64_t rows, int w, const T* __restrict__ src, T* __restrict__ dst,
+                               const int32_t* __restrict__ map) {
+  int64_t g = (int64_t)nm_xcd_block() * blockDim.x + threadIdx.x;
+  if (g >= rows * w) return;
+  int64_t r = g / w;
+  int e = (int)(g - r * w);
+  dst[g] = src[(int64_t)map[r] * w + e];
+}
+
+void permute_rows(int64_t rows, int w, const void* src, void* dst, const int32_t* map, int elem_bytes,
+                  hipStream_t st) {
+  if (elem_bytes == 8)
+    LAUNCH(k_permute_rows<double>, rows * w, st, rows, w, (const double*)src, (double*)dst, map);
+  else
+    LAUNCH(k_permute_rows<float>, rows * w, st, rows, w, (const float*)src, (float*)dst, map);
+}
+
+void api_apply(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg,
+               hipStream_t st) {
+  NM_REQUIRE(ncols > 0, NM_EINVAL, "ncols must be positive");
+  const int eb = cfg.precision == 1 ? 4 : 8;
+  const bool in_disp = !(op == NM_OP_KP || op == NM_OP_EG || op == NM_OP_KPINV);
+  const bool out_disp = !(op == NM_OP_KP || op == NM_OP_EGT || op == NM_OP_KPINV);
+  const int64_t N = P->N, w = 3 * (int64_t)ncols;
+  DBuf<char> xi, yi;
+  const void* xin = X;
+  void* yout = Y;
+  if (in_disp) {
+    xi.alloc((size_t)N * w * eb);
+    permute_rows(N, (int)w, X, xi.p, P->iperm.p, eb, st);
+    xin = xi.p;
+  }
+  if (out_disp) {
+    yi.alloc((size_t)N * w * eb);
+    yout = yi.p;
+  }
+  apply_op(P, op, ncols, xin, yout, cfg, st);
+  if (out_disp) permute_rows(N, (int)w, yi.p, Y, P->perm.p, eb, st);
+  NM_HIP(hipStreamSynchronize(st));
+}
+
+void apply_op(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg, hipStream_t st) {
+  NM_REQUIRE(ncols > 0, NM_EINVAL, "ncols must be positive");
+  if (cfg.precision == 1) {
+    const_cast<nm_pencil*>(P)->ensure_fp32(st);
+    apply_op_t<float>(P, op, ncols, X, Y, cfg, st);
+  } else {
+    apply_op_t<double>(P, op, ncols, X, Y, cfg, st);
+  }
+}
+
+void col_dots(int64_t rows, int ncols, const double* X, int ldx, const double* Y, int ldy, double* out,
+              hipStream_t st) {
+  const int nblk = 512;
+  int64_t rows_per = (rows + nblk - 1) / nblk;
+  DBuf<double> part((size_t)nblk * ncols);
+  hipLaunchKernelGGL(k_coldot_partial, dim3(nblk), dim3(256), 0, st, rows, ncols, X, ldx, Y, ldy, rows_per, part.p);
+  hipLaunchKernelGGL(k_coldot_final, dim3((ncols + 63) / 64), dim3(64), 0, st, nblk, ncols, part.p, out);
+  NM_HIP(hipStreamSynchronize(st));
+}
+
+void KernelProf::before(hipStream_t st, bool& sampled) {
+  sampled = (launches++ % every) == 0;
+  if (!sampled) return;
+  if (used + 2 > (int)pool.size()) {
+    if (pool.size() < 512) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        NM_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+      }
+    } else {
+      harvest();
+    }
+  }
+  NM_HIP(hipEventRecord(pool[used], st));
+}
+void KernelProf::after(hipStream_t st) {
+  NM_HIP(hipEventRecord(pool[used + 1], st));
+  used += 2;
+}
+void KernelProf::harvest() {
+  for (int i = 0; i + 1 < used; i += 2) {
+    NM_HIP(hipEventSynchronize(pool[i + 1]));
+    float t = 0.f;
+    NM_HIP(hipEventElapsedTime(&t, pool[i], pool[i + 1]));
+    ms += t;
+    ++samples;
+  }
+  used = 0;
+}
+KernelProf::~KernelProf() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+void convert_f64_f32(int64_t n, const double* a, float* b, hipStream_t st) {
+  LAUNCH(k_f64_f32, n, st, n, a, b);
+}
+void convert_f32_f64(int64_t n, const float* a, double* b, hipStream_t st) {
+  LAUNCH(k_f32_f64, n, st, n, a, b);
+}
+
+}  // namespace nm
+
+void nm_pencil::ensure_fp32(hipStream_t st) {
+  if (ms32.p) return;
+  auto cv = [&](const nm::DBuf<double>& a, nm::DBuf<float>& b) {
+    b.alloc(std::max<size_t>(a.n, 1));
+    if (a.n) nm::convert_f64_f32((int64_t)a.n, a.p, b.p, st);
+  };
+  cv(ag, ag32); cv(ms, ms32); cv(mdinv, mdinv32);
+  cv(kp, kp32); cv(kpdinv, kpdinv32); cv(eg_val, eg_val32); cv(egt_val, egt_val32);
+  NM_HIP(hipStreamSynchronize(st));
+}

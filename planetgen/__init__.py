@@ -307,10 +307,12 @@ def homogeneous_ball(seed: int = 1906, n_half: int = 4, order: int = 1, jitter: 
 
 
 def three_layer_planet(seed: int = 1906, n_half: int = 20, order: int = 2, pres_order: int = 1,
-                       grf_amp: float = 0.02, jitter: float = 0.1, omega=(0.0, 0.0, 0.0),
+                       grf_amp: float = 0.02, jitter: float = 0.05, omega=(0.0, 0.0, 0.0),
                        gravity: bool = True):
     """Solid inner core r < 0.19, fluid outer core to 0.55, solid mantle to 1.
-    Interface shells are placed so that the radial spacing is nearly uniform."""
+    Interface shells are placed so that the radial spacing is nearly uniform.
+    Vertex jitter 5 % of the local edge length: larger jitter creates the
+    flattest elements, which set the top of the spectrum."""
     l1 = max(1, int(round(n_half * 0.19)))
     l2 = max(l1 + 1, int(round(n_half * 0.55)))
     xyz, tet, layer = cubed_ball(n_half, [(l1, 0.19), (l2, 0.55), (n_half, 1.0)], seed, jitter)
@@ -320,7 +322,7 @@ def three_layer_planet(seed: int = 1906, n_half: int = 20, order: int = 2, pres_
 
 
 def mars_like(seed: int = 1906, n_half: int = 30, order: int = 2, pres_order: int = 1,
-              grf_amp: float = 0.05, jitter: float = 0.1, omega=(0.0, 0.0, 0.1),
+              grf_amp: float = 0.05, jitter: float = 0.05, omega=(0.0, 0.0, 0.1),
               gravity: bool = True):
     """Two-layer body: fluid core r < 0.5, solid mantle with lateral
     heterogeneity."""

@@ -1,0 +1,135 @@
+"""GPU eigensolves against the oracle's reference solutions."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from conftest import planet as make_planet
+from oracle.assemble import Pencil as OPencil
+from oracle import solve as S
+from oracle import rotation as RT
+
+pytestmark = pytest.mark.gpu
+
+
+def _clusters(w, rel=1e-6):
+    groups, cur = [], [0]
+    for i in range(1, len(w)):
+        if w[i] - w[i - 1] <= rel * abs(w[i]):
+            cur.append(i)
+        else:
+            groups.append(cur)
+            cur = [i]
+    groups.append(cur)
+    return groups
+
+
+def _check_vectors(X, Xref, M, w):
+    """Eigenvectors: per cluster of (near-)equal eigenvalues the M-orthogonal
+    projectors agree (any orthonormal basis of a cluster is correct)."""
+    for g in _clusters(w):
+        if len(g) and g[-1] == len(w) - 1:
+            continue  # the last cluster may be cut by nev
+        A, B = X[:, g], Xref[:, g]
+        s = np.linalg.svd(A.T @ (M @ B), compute_uv=False)
+        assert s.min() > 1 - 1e-7, (g, s)
+
+
+def test_c1_ball_matches_dense():
+    """Homogeneous ball, P1, ~3k tets: lowest 30 pairs in [0.5, 40] with the
+    degree-40 filter; eigenvalues within 1e-10 relative, residuals <= 1e-10."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("homogeneous_ball", n_half=4, order=1)
+    print("\n[case] C1 ball", flush=True)
+    G = nm.Pencil(d)
+    r = G.filtered_eig(0.5, 40.0, 30, 1e-10, degree=40, block=8)
+    O = OPencil(d)
+    A, M = O.AG.toarray(), O.M.toarray()
+    w, Xr = S.dense_window(A, M, 0.5, 40.0)
+    assert r.count == 30
+    assert np.abs(r.lam - w[:30]).max() <= 1e-10 * w[29]
+    assert r.resid.max() <= 1e-10
+    X = r.X.cpu().numpy()
+    np.testing.assert_allclose(X.T @ M @ X, np.eye(30), atol=1e-9)
+    _check_vectors(X, Xr[:, :30], O.M, w[:30])
+
+
+def _cowling_reference(O, sigma, k):
+    """Eigenvalues of the Cowling pencil nearest sigma: ARPACK shift-invert
+    (scipy eigsh), the shifted solve done exactly by a sparse LU of the
+    saddle-point system [[A_G - s M, E_G], [E_G^T, -K_p]] (exact Schur
+    complement)."""
+    n, n_p = O.n, O.n_p
+    K = sp.bmat([[O.AG - sigma * O.M, O.EG], [O.EG.T, -O.Kp]], format="csc")
+    lu = spla.splu(K)
+    kp = O.kp_direct()
+    Aop = spla.LinearOperator((n, n), matvec=lambda x: O.cowling_apply(x, kp), dtype=float)
+    Sop = spla.LinearOperator((n, n), matvec=lambda f: lu.solve(np.concatenate([f, np.zeros(n_p)]))[:n],
+                              dtype=float)
+    lam, V = spla.eigsh(Aop, k=k, M=O.M, sigma=sigma, OPinv=Sop, which="LM", tol=1e-13)
+    order = np.argsort(lam)
+    return lam[order], V[:, order]
+
+
+def test_layered_cowling_matches_shift_invert():
+    """Three-layer planet (solid/fluid/solid), P2 displacement + P1 pressure,
+    gravity, Cowling: all pairs in [1, 12] within 1e-9 relative of the
+    oracle's exact-Schur shift-invert solution."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    print("\n[case] layered P2/P1 n_half=4", flush=True)
+    G = nm.Pencil(d)
+    r = G.filtered_eig(1.0, 12.0, 200, 1e-9, block=8, verbose=1)
+    O = OPencil(d)
+    lam, _ = _cowling_reference(O, 6.0, min(3 * max(r.count, 10), 80))
+    ref = lam[(lam >= 1.0) & (lam <= 12.0)]
+    assert r.count == len(ref) and r.count > 0
+    assert np.abs(r.lam - ref).max() <= 1e-9 * ref.max()
+    assert r.resid.max() <= 1e-9
+
+
+def test_fp32_filter_same_eigenvalues():
+    """FP32 filter + FP64 Rayleigh-Ritz reaches the FP64 eigenvalues."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("homogeneous_ball", n_half=4, order=1)
+    G = nm.Pencil(d)
+    r64 = G.filtered_eig(0.5, 40.0, 30, 1e-10, degree=40, block=8)
+    r32 = G.filtered_eig(0.5, 40.0, 30, 1e-6, degree=40, block=8, precision=1, allow_partial=True)
+    n = min(r32.count, 30)
+    print("fp32 resid max %.2e" % r32.resid.max(), flush=True)
+    assert np.abs(r32.lam[:n] - r64.lam[:n]).max() <= 1e-8 * r64.lam[:n].max()
+
+
+def test_rotation_projection_matches_oracle():
+    """Projected Coriolis problem from the GPU basis: the oracle's projection
+    of the same basis gives the same frequencies (1e-12), and R = 0 gives
+    omega = sqrt(lambda)."""
+    import paper_1906_11082_amd as nm
+    d = dict(make_planet("homogeneous_ball", n_half=4, order=1))
+    d["omega"] = (0.0, 0.0, 0.2)
+    G = nm.Pencil(d)
+    r = G.filtered_eig(0.5, 40.0, 30, 1e-10, degree=40, block=8)
+    rot = G.project_rotation(r, 4.0, 36.0)
+    O = OPencil(d)
+    X = r.X.cpu().numpy()
+    om, U, _ = RT.project_rotation(r.lam, X, lambda V: O.R @ V, 4.0, 36.0)
+    assert rot.count == len(om)
+    assert np.abs(rot.omega - np.sort(om)).max() <= 1e-12 * om.max()
+    Ug = rot.U.cpu().numpy()
+    Mx = O.M
+    Gm = Ug.conj().T @ (Mx @ Ug) - 2j * (Ug.conj().T @ (O.R @ Ug)) / (rot.omega[:, None] + rot.omega[None, :])
+    np.testing.assert_allclose(Gm, np.eye(rot.count), atol=1e-9)
+    d0 = dict(d, omega=(0.0, 0.0, 0.0))
+    G0 = nm.Pencil(d0)
+    r0 = G0.filtered_eig(0.5, 40.0, 30, 1e-10, degree=40, block=8)
+    rot0 = G0.project_rotation(r0, 0.5, 40.0)
+    assert np.abs(rot0.omega - np.sqrt(r0.lam)).max() <= 1e-13 * np.sqrt(r0.lam).max()
+
+
+def test_empty_window_returns_no_pairs():
+    import paper_1906_11082_amd as nm
+    d = make_planet("homogeneous_ball", n_half=3, order=1)
+    G = nm.Pencil(d)
+    r = G.filtered_eig(0.01, 0.05, 5, 1e-8, degree=30, block=4, max_basis=40, allow_partial=True)
+    assert r.count == 0
