@@ -813,6 +813,7 @@ void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStre
     hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(N)), dim3(256), 0, st, N, P->row_ptr.p, P->col.p, P->ms.p,
                        P->mdinv.p);
   }
+  build_row_groups(P, st);
   Ke.release();
   Kf.release();
 

@@ -119,6 +119,11 @@ struct nm_pencil {
   // (Morton) order of the displacement nodes: internal = perm[canonical],
   // canonical = iperm[internal]
   nm::DBuf<int32_t> node_geom, pres_geom, perm, iperm;
+  // row groups of the node graph (grouped mass solve): grp_rows 0 -> per-row kernel
+  int grp_rows = 0;
+  nm::DBuf<int32_t> grp_ptr, grp_col;
+  nm::DBuf<double> grp_coef;
+  int grouped = 1;  // 0 forces the per-row kernels
   rocblas_handle blas = nullptr;
   void ensure_fp32(hipStream_t st);
 };
@@ -126,6 +131,8 @@ struct nm_pencil {
 namespace nm {
 // pattern + assembly (nm_assemble.hip)
 void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStream_t st);
+// row groups (nm_groups.hip)
+void build_row_groups(nm_pencil* P, hipStream_t st);
 
 // operators (nm_ops.hip)
 // Sampled HIP-event timing of the hot kernel (a middle Chebyshev-Jacobi

@@ -16,6 +16,7 @@
 // The last step of the M solve is fused with the three-term Chebyshev
 // filter update (W_{k+1} = a1 (B W_k - c W_k) + a2 W_{k-1}, Y += mu W_{k+1}).
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 #include "nm_internal.h"
@@ -362,6 +363,101 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
   }
 }
 
+
+// Row-group Chebyshev-Jacobi step (same arithmetic and modes as k_cj_step).
+// Rows are processed in groups of R consecutive rows of the Morton order;
+// each lane owns one V-wide entry slot of all R rows and walks the union of
+// their columns once, with an R-wide coefficient row per union column
+// (zeros where a row lacks the column).  A gathered neighbour row serves
+// every row of the group that touches it, so the gather volume (the
+// bottleneck: L2 -> CU traffic) drops by |sum of row lengths| / |union|.
+template <class T, int V, int R>
+__global__ __launch_bounds__(256) void k_cj_group(
+    uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
+    const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
+    const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
+    T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc) {
+  const uint32_t wl = w / V;
+  const uint32_t ngroups = (N + R - 1) / R;
+  const uint32_t g = lane_id();
+  if (g >= ngroups * wl) return;
+  const uint32_t grp = g / wl, e = (g - grp * wl) * V;
+  const uint32_t r0 = grp * R;
+  Vx<T, V> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[r].v[i] = T(0);
+  const int32_t l0 = gptr[grp], l1 = gptr[grp + 1];
+  for (int32_t l = l0; l < l1; l += 4) {
+    uint32_t c[4];
+    bool in[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      in[u] = l + u < l1;
+      c[u] = (uint32_t)gcol[in[u] ? l + u : l0];
+    }
+    Vx<T, V> x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = ldv<T, V>(ycur + (size_t)(c[u] * w + e));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!in[u]) continue;
+      const T* cf = gcoef + (size_t)(l + u) * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T a = cf[r];
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[r].v[i] += a * x[u].v[i];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t row = r0 + r;
+    if (row >= N) break;
+    const size_t o = (size_t)row * w + e;
+    const Vx<T, V> yc = ldv<T, V>(ycur + o);
+    const Vx<T, V> ff = ldv<T, V>(f + o);
+    Vx<T, V> yp;
+    if (prev_zero) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) yp.v[i] = T(0);
+    } else {
+      yp = ldv<T, V>(yprev + o);
+    }
+    const T bd = beta * dinv[row];
+    Vx<T, V> z;
+#pragma unroll
+    for (int i = 0; i < V; ++i) z.v[i] = yc.v[i] + alpha * (yc.v[i] - yp.v[i]) + bd * (ff.v[i] - acc[r].v[i]);
+    if (mode == 0) {
+      stv<T, V>(out + o, z);
+      continue;
+    }
+    const Vx<T, V> wi = ldv<T, V>(win + o);
+    Vx<T, V> wo;
+#pragma unroll
+    for (int i = 0; i < V; ++i) wo.v[i] = a1 * (z.v[i] - cs * wi.v[i]);
+    if (a2 != T(0)) {
+      const Vx<T, V> wp = ldv<T, V>(wprev + o);
+#pragma unroll
+      for (int i = 0; i < V; ++i) wo.v[i] += a2 * wp.v[i];
+    }
+    stv<T, V>(wout + o, wo);
+    if (ymode == 1) {
+      Vx<T, V> yy;
+#pragma unroll
+      for (int i = 0; i < V; ++i) yy.v[i] = mu0 * wi.v[i] + mu * wo.v[i];
+      stv<T, V>(Yacc + o, yy);
+    } else if (ymode == 2) {
+      Vx<T, V> yy = ldv<T, V>(Yacc + o);
+#pragma unroll
+      for (int i = 0; i < V; ++i) yy.v[i] += mu * wo.v[i];
+      stv<T, V>(Yacc + o, yy);
+    }
+  }
+}
+
 template <class T>
 __global__ void k_scale_copy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
   int64_t g = gtid();
@@ -434,11 +530,55 @@ void launch_cj_first(int64_t rows, int w, const T* dinv, const T* f, T inv_theta
   int v = pick_v<T>(w);
   NM_LAUNCH_V(k_cj_first, T, v, rows * (w / v), st, (uint32_t)rows, (uint32_t)w, dinv, f, inv_theta, y);
 }
+// row-group launch plan for the mass solve (displacement rows)
+struct GroupPlan {
+  bool on = false;
+  int R = 0;
+  const int32_t *gptr = nullptr, *gcol = nullptr;
+  const void* gcoef = nullptr;
+};
+// FP64 only: in FP32 the per-row kernel measured as fast or faster.
+template <class T>
+GroupPlan group_plan(const nm_pencil* P, int b) {
+  GroupPlan tp;
+  if (sizeof(T) != 8 || !P->grouped || P->grp_rows <= 0 || b < 2) return tp;
+  tp.on = true;
+  tp.R = P->grp_rows;
+  tp.gptr = P->grp_ptr.p;
+  tp.gcol = P->grp_col.p;
+  tp.gcoef = P->grp_coef.p;
+  return tp;
+}
+
+template <class T>
+void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const T* f, const T* ycur, const T* yprev,
+                     T alpha, T beta, int prev_zero, int mode, T* out, const T* win, const T* wprev, T a1, T cs, T a2,
+                     int ymode, T mu0, T mu, T* wout, T* Yacc, hipStream_t st) {
+  const int v = pick_v<T>(w);
+  const int64_t lanes = (N + tp.R - 1) / tp.R * (w / v);
+  const T* cf = (const T*)tp.gcoef;
+#define NM_GRP(VV, RR)                                                                                              \
+  hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,     \
+                     tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,  \
+                     cs, a2, ymode, mu0, mu, wout, Yacc)
+  if (tp.R == 8) {
+    if (v == 4) NM_GRP(4, 8); else if (v == 2) NM_GRP(2, 8); else NM_GRP(1, 8);
+  } else {
+    if (v == 4) NM_GRP(4, 4); else if (v == 2) NM_GRP(2, 4); else NM_GRP(1, 4);
+  }
+#undef NM_GRP
+}
+
 template <class T>
 void launch_cj_step(int64_t rows, int w, const int32_t* rp, const int32_t* col, const T* val, const T* dinv,
                     const T* f, const T* ycur, const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out,
                     const T* win, const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc,
-                    hipStream_t st) {
+                    hipStream_t st, const GroupPlan* tp = nullptr) {
+  if (tp && tp->on) {
+    launch_cj_group<T>(*tp, rows, w, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1, cs,
+                       a2, ymode, mu0, mu, wout, Yacc, st);
+    return;
+  }
   int v = pick_v<T>(w);
   NM_LAUNCH_V(k_cj_step, T, v, rows * (w / v), st, (uint32_t)rows, (uint32_t)w, rp, col, val, dinv, f, ycur, yprev,
               alpha, beta, prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, mu0, mu, wout, Yacc);
@@ -537,6 +677,7 @@ void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, 
   NM_REQUIRE(kM >= 2, NM_EINVAL, "the M solve needs at least 2 Chebyshev steps");
   auto m = mats<T>(P);
   ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, kM);
+  const GroupPlan tp = group_plan<T>(P, b);
   a_apply<T>(P, b, X, w.f.p, w.ya.p, 1.0 / cc.theta, kP, w, st);
   const int64_t N = P->N;
   const int wd = 3 * b;
@@ -548,17 +689,17 @@ void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, 
       if (prof && j >= 2) prof->before(st, sampled);
       launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, prev, nullptr, nullptr, T(0), T(0), T(0), 0, T(0),
-                        T(0), nullptr, nullptr, st);
+                        T(0), nullptr, nullptr, st, &tp);
       if (sampled) prof->after(st);
       std::swap(cur, prev);
     } else if (!u.on) {
       launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, Z, nullptr, nullptr, T(0), T(0), T(0), 0, T(0), T(0),
-                        nullptr, nullptr, st);
+                        nullptr, nullptr, st, &tp);
     } else {
       launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 1, nullptr, (const T*)u.win, (const T*)u.wprev, (T)u.a1,
-                        (T)u.cs, (T)u.a2, u.ymode, (T)u.mu0, (T)u.mu, (T*)u.wout, (T*)u.Y, st);
+                        (T)u.cs, (T)u.a2, u.ymode, (T)u.mu0, (T)u.mu, (T*)u.wout, (T*)u.Y, st, &tp);
     }
   }
 }
@@ -698,13 +839,14 @@ static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* 
       NM_REQUIRE(cfg.kM >= 2, NM_EINVAL, "kM must be >= 2");
       DBuf<T> ya(N * wd), yb(N * wd);
       ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, cfg.kM);
+      const GroupPlan tp = group_plan<T>(P, b);
       launch_cj_first<T>(N, wd, m.mdinv, X, (T)(1.0 / cc.theta), ya.p, st);
       T *cur = ya.p, *prev = yb.p;
       for (int j = 1; j < cfg.kM; ++j) {
         T* out = j == cfg.kM - 1 ? Y : prev;
         launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, X, cur, prev, (T)cc.alpha[j - 1],
                           (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, out, nullptr, nullptr, T(0), T(0), T(0), 0, T(0),
-                          T(0), nullptr, nullptr, st);
+                          T(0), nullptr, nullptr, st, &tp);
         std::swap(cur, prev);
       }
       NM_HIP(hipStreamSynchronize(st));
