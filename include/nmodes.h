@@ -135,12 +135,14 @@ typedef struct {
                           pencil has fluid, else damping), 0 damping below a, 1 factor
                           lambda/b, 2 no damping below a */
   int32_t verbose;     /* 0 quiet, 1 per-block log on stderr */
-  double minv_tol;     /* M-solve bound inside the filter (0 = 1e-10 FP64, 1e-7 FP32) */
+  double minv_tol;     /* M-solve bound inside the filter (0: 0.3 tol clamped to [1e-12, 1e-7] in FP64, 1e-7 in FP32) */
   double kp_tol;       /* K_p-solve bound (0 = 1e-13 FP64, 1e-7 FP32) */
   double lmin, lmax;   /* spectrum bounds of M^{-1}A; lmax <= lmin: estimate */
   double guard;        /* transition width beyond b as a fraction of b (0 = 1.0) */
   uint64_t seed;       /* start block seed */
   void* stream;        /* hipStream_t */
+  int32_t refine;      /* at most this many FP64 refinement passes of the window pairs
+                          (0 = 3, -1 = none; see nm_filtered_eig) */
 } nm_eig_opts;
 
 typedef struct {
@@ -163,6 +165,11 @@ typedef struct {
      stream, their mean duration, and its algorithmic bytes per launch */
   int64_t hot_launches, hot_samples;
   double hot_ms, hot_bytes;
+  /* FP64 refinement: passes run, degree of the last low-pass polynomial,
+     their wall time and column B-applications */
+  int32_t refine_passes, refine_degree;
+  double refine_seconds;
+  int64_t refine_bapps;
 } nm_eig_result;
 
 typedef struct {
@@ -229,7 +236,16 @@ nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, v
 /* Eigenpairs of the Cowling pencil with a <= omega^2 <= b: the min(nev,
  * count) smallest, by polynomial-filtered block Lanczos in the M-inner
  * product with Rayleigh-Ritz on (A, M) (Sec. 6.1).  tol bounds the
- * residual of every returned pair. */
+ * residual of every returned pair.  Rounding inside the filter (FP64:
+ * about eps64 times the degree; precision 1, the filter in FP32 values,
+ * vectors and accumulation: eps32) leaves the window residuals at a floor
+ * near eps * lambda_max / lambda.  The Lanczos therefore stops when they are
+ * below tol or no longer improve, and the window pairs are refined in FP64:
+ * each pass applies a Chebyshev low-pass polynomial (1 at b, small beyond a
+ * cut-off chosen from the current floor) to them and runs Rayleigh-Ritz on
+ * (A, M) over the Krylov basis together with the refined vectors.  NM_PARTIAL:
+ * the pairs returned are those found, some with residual above tol, or the
+ * basis cap was reached first. */
 nm_status nm_filtered_eig(const nm_pencil* p, double a, double b, int32_t nev, double tol,
                           const nm_eig_opts* opts, nm_eig_result** out);
 

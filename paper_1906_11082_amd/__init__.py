@@ -62,7 +62,7 @@ class _EigOpts(C.Structure):
     _fields_ = [("degree", C.c_int32), ("block", C.c_int32), ("precision", C.c_int32), ("max_basis", C.c_int32),
                 ("null_filter", C.c_int32), ("verbose", C.c_int32), ("minv_tol", C.c_double),
                 ("kp_tol", C.c_double), ("lmin", C.c_double), ("lmax", C.c_double), ("guard", C.c_double),
-                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+                ("seed", C.c_uint64), ("stream", C.c_void_p), ("refine", C.c_int32)]
 
 
 class _EigResult(C.Structure):
@@ -71,7 +71,8 @@ class _EigResult(C.Structure):
                 ("kP", C.c_int32), ("block", C.c_int32), ("basis", C.c_int32), ("bapps", C.c_int64),
                 ("lmin", C.c_double), ("lmax", C.c_double), ("seconds", C.c_double), ("bytes", C.c_double),
                 ("filter_seconds", C.c_double), ("hot_launches", C.c_int64), ("hot_samples", C.c_int64),
-                ("hot_ms", C.c_double), ("hot_bytes", C.c_double)]
+                ("hot_ms", C.c_double), ("hot_bytes", C.c_double), ("refine_passes", C.c_int32),
+                ("refine_degree", C.c_int32), ("refine_seconds", C.c_double), ("refine_bapps", C.c_int64)]
 
 
 class _RotResult(C.Structure):
@@ -169,7 +170,9 @@ class EigResult:
         self.stats = dict(degree=r.degree, kM=r.kM, kP=r.kP, block=r.block, basis=r.basis, bapps=r.bapps,
                           lmin=r.lmin, lmax=r.lmax, seconds=r.seconds, bytes=r.bytes,
                           filter_seconds=r.filter_seconds, hot_launches=r.hot_launches,
-                          hot_samples=r.hot_samples, hot_ms=r.hot_ms, hot_bytes=r.hot_bytes)
+                          hot_samples=r.hot_samples, hot_ms=r.hot_ms, hot_bytes=r.hot_bytes,
+                          refine_passes=r.refine_passes, refine_degree=r.refine_degree,
+                          refine_seconds=r.refine_seconds, refine_bapps=r.refine_bapps)
         self._ptr = ptr
         self.n = r.n
         self.X = None
@@ -282,9 +285,9 @@ class Pencil:
 
     def filtered_eig(self, a, b, nev, tol, degree=0, block=0, precision=0, max_basis=0, null_filter=-1,
                      verbose=0, minv_tol=0.0, kp_tol=0.0, lmin=0.0, lmax=0.0, guard=0.0, seed=1,
-                     allow_partial=False):
+                     allow_partial=False, refine=0):
         o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, lmin, lmax,
-                     guard, seed, _stream())
+                     guard, seed, _stream(), refine)
         r = C.POINTER(_EigResult)()
         st = _lib.nm_filtered_eig(self._h, a, b, nev, tol, C.byref(o), C.byref(r))
         if st == NM_PARTIAL and allow_partial and r:

@@ -310,7 +310,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   ApplyCfg cfg;
   KernelProf prof;
   cfg.prof = &prof;
-  double mtol = o.minv_tol > 0 ? o.minv_tol : (prec ? 1e-7 : 1e-10);
+  // default mass-solve bound: the residual floor it leaves is about half of it
+  double mtol = o.minv_tol > 0 ? o.minv_tol : (prec ? 1e-7 : std::min(1e-7, std::max(1e-12, 0.3 * tol)));
   double ptol = o.kp_tol > 0 ? o.kp_tol : (prec ? 1e-7 : 1e-13);
   cfg.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, mtol);
   cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, ptol);
@@ -421,6 +422,27 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
                             hipMemcpyDeviceToDevice, st));
   };
 
+  // symmetric eigenproblem (col-major n x n, ascending values, vectors in columns):
+  // cyclic Jacobi on the host for small orders, rocSOLVER dsyevd otherwise
+  DBuf<rocblas_int> info(1);
+  auto sym_eig = [&](int nn, std::vector<double>& A, std::vector<double>& wv, std::vector<double>& Sv) {
+    if (nn <= 160) {
+      jacobi_eig(nn, A, wv, &Sv);
+      return;
+    }
+    DBuf<double> hd((size_t)nn * nn), wd(nn), ed(nn);
+    NM_HIP(hipMemcpyAsync(hd.p, A.data(), 8 * (size_t)nn * nn, hipMemcpyHostToDevice, st));
+    NM_BLAS(rocsolver_dsyevd(bl.h, rocblas_evect_original, rocblas_fill_upper, nn, hd.p, nn, wd.p, ed.p, info.p));
+    wv.resize(nn);
+    Sv.resize((size_t)nn * nn);
+    NM_HIP(hipMemcpyAsync(wv.data(), wd.p, 8 * (size_t)nn, hipMemcpyDeviceToHost, st));
+    NM_HIP(hipMemcpyAsync(Sv.data(), hd.p, 8 * (size_t)nn * nn, hipMemcpyDeviceToHost, st));
+    NM_HIP(hipStreamSynchronize(st));
+  };
+  // convergence of the Ritz values of p(B): residual estimate <= mu_tol * max |Ritz value|;
+  // an FP32 filter cannot take them much below 1e-6
+  const double mu_tol = prec ? 1e-5 : 1e-8;
+
   uint64_t seed = o.seed;
   int64_t fresh = 0;
   auto random_block = [&]() {
@@ -435,9 +457,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   // results of the last Rayleigh-Ritz
   std::vector<double> th_sel, res_sel;
   std::vector<int> idx_sel;
-  DBuf<double> HA, th_d, ework;
-  DBuf<rocblas_int> info(1);
   int last_count = -1;
+  double prev_res_max = 0.0;
   bool converged = false;
   int Kc_last = 0;
   std::vector<double> Ysel;  // col-major Kc x nsel
@@ -500,38 +521,89 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     put_block(K);
     K += bs;
 
-    // ---- Rayleigh-Ritz with (A, M) on V[:, :K]
-    const int Kc = K;
-    if (Kc < 2 * bs && Kc + bs <= Kmax) continue;
-    HA.alloc((size_t)Kc * Kc);
-    th_d.alloc(Kc);
-    ework.alloc(Kc);
-    bl.tn(n, Kc, Kc, V.p, Kmax, AV.p, Kmax, HA.p);
+    // ---- Ritz values of p(B) on the filtered part of the basis, their
+    // residual estimates, and Rayleigh-Ritz with (A, M) restricted to the
+    // span of the Ritz vectors of p(B) whose value is at least the filter's
+    // window-edge level tau.  Restricting the Rayleigh-Ritz to that span keeps
+    // out combinations of filtered-through directions far below the window
+    // (the fluid null space) and above it, whose Rayleigh quotients can fall
+    // inside the window without being eigenvalues.
+    const int Kf = K - bs;  // columns whose images are in the basis
+    if (Kf < bs && K + bs <= Kmax) continue;
+    std::vector<double> w, S;
     {
-      std::vector<double> h((size_t)Kc * Kc);
-      NM_HIP(hipMemcpyAsync(h.data(), HA.p, 8 * h.size(), hipMemcpyDeviceToHost, st));
-      NM_HIP(hipStreamSynchronize(st));
-      for (int i = 0; i < Kc; ++i)
-        for (int q = 0; q < i; ++q) h[i + (size_t)q * Kc] = h[q + (size_t)i * Kc] = 0.5 * (h[i + (size_t)q * Kc] + h[q + (size_t)i * Kc]);
-      NM_HIP(hipMemcpyAsync(HA.p, h.data(), 8 * h.size(), hipMemcpyHostToDevice, st));
+      std::vector<double> Hs((size_t)Kf * Kf);
+      for (int q = 0; q < Kf; ++q)
+        for (int i = 0; i < Kf; ++i)
+          Hs[i + (size_t)q * Kf] = 0.5 * (H[(size_t)i + (size_t)q * Kmax] + H[(size_t)q + (size_t)i * Kmax]);
+      sym_eig(Kf, Hs, w, S);
     }
-    NM_BLAS(rocsolver_dsyevd(bl.h, rocblas_evect_original, rocblas_fill_upper, Kc, HA.p, Kc, th_d.p, ework.p, info.p));
-    std::vector<double> th(Kc);
-    NM_HIP(hipMemcpyAsync(th.data(), th_d.p, 8 * Kc, hipMemcpyDeviceToHost, st));
-    NM_HIP(hipStreamSynchronize(st));
+    bool mu_ok = true;
+    std::vector<int> big;
+    {
+      double wmax = 0;
+      for (double x : w) wmax = std::max(wmax, std::fabs(x));
+      for (int i = 0; i < Kf; ++i) {
+        if (w[i] < tau) continue;
+        big.push_back(i);
+        // residual estimate || H[K-bs:K, Kf-bs:Kf] s_i[Kf-bs:Kf] ||
+        double r2 = 0;
+        for (int p = 0; p < bs; ++p) {
+          double sum = 0;
+          for (int q = 0; q < bs; ++q)
+            sum += H[(size_t)(Kf + p) + (size_t)(Kf - bs + q) * Kmax] * S[(size_t)(Kf - bs + q) + (size_t)i * Kf];
+          r2 += sum * sum;
+        }
+        if (std::sqrt(r2) > mu_tol * wmax) mu_ok = false;
+      }
+    }
+    const int nb = (int)big.size();
+    std::vector<double> Yb((size_t)Kf * std::max(nb, 1));  // Kf x nb, col-major
+    for (int q = 0; q < nb; ++q)
+      std::copy(S.begin() + (size_t)big[q] * Kf, S.begin() + (size_t)(big[q] + 1) * Kf, Yb.begin() + (size_t)q * Kf);
+    std::vector<double> th, Z;
+    if (nb > 0) {
+      // G = Yb^T (V_f^T A V_f) Yb on the device, then its eigenpairs
+      DBuf<double> Ybd((size_t)Kf * nb), HAf((size_t)Kf * Kf), T1((size_t)Kf * nb), Gd2((size_t)nb * nb);
+      NM_HIP(hipMemcpyAsync(Ybd.p, Yb.data(), 8 * Yb.size(), hipMemcpyHostToDevice, st));
+      bl.tn(n, Kf, Kf, V.p, Kmax, AV.p, Kmax, HAf.p);
+      const double one = 1.0, zero = 0.0;
+      NM_BLAS(rocblas_dgemm(bl.h, rocblas_operation_none, rocblas_operation_none, Kf, nb, Kf, &one, HAf.p, Kf, Ybd.p,
+                            Kf, &zero, T1.p, Kf));
+      NM_BLAS(rocblas_dgemm(bl.h, rocblas_operation_transpose, rocblas_operation_none, nb, nb, Kf, &one, Ybd.p, Kf,
+                            T1.p, Kf, &zero, Gd2.p, nb));
+      std::vector<double> Gh((size_t)nb * nb);
+      NM_HIP(hipMemcpyAsync(Gh.data(), Gd2.p, 8 * Gh.size(), hipMemcpyDeviceToHost, st));
+      NM_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < nb; ++i)
+        for (int q = 0; q < i; ++q)
+          Gh[i + (size_t)q * nb] = Gh[q + (size_t)i * nb] = 0.5 * (Gh[i + (size_t)q * nb] + Gh[q + (size_t)i * nb]);
+      sym_eig(nb, Gh, th, Z);
+    }
     idx_sel.clear();
-    for (int i = 0; i < Kc; ++i)
+    for (int i = 0; i < nb; ++i)
       if (th[i] >= a && th[i] <= b) idx_sel.push_back(i);
     const int ns = (int)idx_sel.size();
     th_sel.assign(ns, 0.0);
     res_sel.assign(ns, 0.0);
+    // coefficients of the selected Ritz vectors in V_f: Yb Z[:, sel] (Kf x ns)
+    std::vector<double> Ynew((size_t)Kf * std::max(ns, 0), 0.0);
+    for (int q = 0; q < ns; ++q) {
+      const double* zc = Z.data() + (size_t)idx_sel[q] * nb;
+      double* yc = Ynew.data() + (size_t)q * Kf;
+      for (int k = 0; k < nb; ++k) {
+        const double zk = zc[k];
+        const double* bc = Yb.data() + (size_t)k * Kf;
+        for (int i = 0; i < Kf; ++i) yc[i] += zk * bc[i];
+      }
+    }
     bool res_ok = ns > 0;
     if (ns > 0) {
-      // eigenvectors of the selected Ritz values are contiguous (ascending)
-      const double* Y = HA.p + (size_t)idx_sel[0] * Kc;
-      DBuf<double> X((size_t)n * ns), AX((size_t)n * ns), MX((size_t)n * ns), th_dev(ns), rn(ns), mn(ns);
-      bl.nn(n, Kc, ns, 1.0, V.p, Kmax, Y, Kc, 0.0, X.p, ns);
-      bl.nn(n, Kc, ns, 1.0, AV.p, Kmax, Y, Kc, 0.0, AX.p, ns);
+      DBuf<double> Yd((size_t)Kf * ns), X((size_t)n * ns), AX((size_t)n * ns), MX((size_t)n * ns), th_dev(ns),
+          rn(ns), mn(ns);
+      NM_HIP(hipMemcpyAsync(Yd.p, Ynew.data(), 8 * Ynew.size(), hipMemcpyHostToDevice, st));
+      bl.nn(n, Kf, ns, 1.0, V.p, Kmax, Yd.p, Kf, 0.0, X.p, ns);
+      bl.nn(n, Kf, ns, 1.0, AV.p, Kmax, Yd.p, Kf, 0.0, AX.p, ns);
       mprod(X.p, MX.p, ns);
       for (int i = 0; i < ns; ++i) th_sel[i] = th[idx_sel[i]];
       NM_HIP(hipMemcpyAsync(th_dev.p, th_sel.data(), 8 * ns, hipMemcpyHostToDevice, st));
@@ -547,57 +619,185 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
         if (!(res_sel[i] <= tol)) res_ok = false;
       }
     }
-    // Ritz values of p(B) on the filtered part of the basis and their residual estimates
-    bool mu_ok = true;
-    int nbig = 0;
-    {
-      const int Kf = K - bs;  // columns whose images are in the basis
-      std::vector<double> Hs((size_t)Kf * Kf), w, S;
-      for (int q = 0; q < Kf; ++q)
-        for (int i = 0; i < Kf; ++i)
-          Hs[i + (size_t)q * Kf] = 0.5 * (H[(size_t)i + (size_t)q * Kmax] + H[(size_t)q + (size_t)i * Kmax]);
-      if (Kf <= 400) {
-        jacobi_eig(Kf, Hs, w, &S);
-      } else {
-        DBuf<double> hd((size_t)Kf * Kf), wd(Kf), ed(Kf);
-        NM_HIP(hipMemcpyAsync(hd.p, Hs.data(), 8 * Hs.size(), hipMemcpyHostToDevice, st));
-        NM_BLAS(rocsolver_dsyevd(bl.h, rocblas_evect_original, rocblas_fill_upper, Kf, hd.p, Kf, wd.p, ed.p, info.p));
-        w.resize(Kf);
-        S.resize((size_t)Kf * Kf);
-        NM_HIP(hipMemcpyAsync(w.data(), wd.p, 8 * Kf, hipMemcpyDeviceToHost, st));
-        NM_HIP(hipMemcpyAsync(S.data(), hd.p, 8 * S.size(), hipMemcpyDeviceToHost, st));
-        NM_HIP(hipStreamSynchronize(st));
-      }
-      double wmax = 0;
-      for (double x : w) wmax = std::max(wmax, std::fabs(x));
-      for (int i = 0; i < Kf; ++i) {
-        if (w[i] < tau) continue;
-        ++nbig;
-        // residual estimate || H[K-bs:K, Kf-bs:Kf] s_i[Kf-bs:Kf] ||
-        double r2 = 0;
-        for (int p = 0; p < bs; ++p) {
-          double s = 0;
-          for (int q = 0; q < bs; ++q)
-            s += H[(size_t)(Kf + p) + (size_t)(Kf - bs + q) * Kmax] * S[(size_t)(Kf - bs + q) + (size_t)i * Kf];
-          r2 += s * s;
-        }
-        if (std::sqrt(r2) > 1e-8 * wmax) mu_ok = false;
-      }
-    }
     if (o.verbose)
       fprintf(stderr, "[nmodes] block %d basis %d window-pairs %d resid-max %.2e big-mu %d mu-ok %d t=%.2fs\n", j, K,
-              ns, ns ? *std::max_element(res_sel.begin(), res_sel.end()) : 0.0, nbig, (int)mu_ok, clock.s());
+              ns, ns ? *std::max_element(res_sel.begin(), res_sel.end()) : 0.0, nb, (int)mu_ok, clock.s());
     bool stable = ns == last_count;
     last_count = ns;
-    Kc_last = Kc;
-    Ysel.assign((size_t)Kc * std::max(ns, 0), 0.0);
-    if (ns) NM_HIP(hipMemcpy(Ysel.data(), HA.p + (size_t)idx_sel[0] * Kc, 8 * Ysel.size(), hipMemcpyDeviceToHost));
-    if (res_ok && stable && mu_ok) {
+    Kc_last = Kf;
+    Ysel = std::move(Ynew);
+    // Rounding in the filter (FP64: eps64 times the degree; FP32: eps32) puts
+    // noise into every spectral component, which the residual weighs by
+    // lambda_j / lambda: the window residuals stall at a floor.  Stop when
+    // they are below tol or have stopped improving (refined below).
+    const double res_max = ns ? *std::max_element(res_sel.begin(), res_sel.end()) : 0.0;
+    const bool stalled = ns > 0 && prev_res_max > 0 && res_max > 0.5 * prev_res_max;
+    prev_res_max = res_max;
+    if ((res_ok || stalled) && stable && mu_ok) {
       converged = true;
       break;
     }
     if (K + bs > Kmax) break;
   }
+
+  // ---------------- FP64 refinement of the window pairs
+  DBuf<double> Xref;  // refined Ritz vectors (internal order), [n][th_sel.size()]
+  int refine_passes = 0, kq = 0;
+  int64_t refine_bapps = 0;
+  Timer rclock;
+  auto max_res = [&]() { return res_sel.empty() ? 0.0 : *std::max_element(res_sel.begin(), res_sel.end()); };
+  if (o.refine >= 0 && !th_sel.empty() && max_res() > tol) {
+    const int npass = o.refine > 0 ? o.refine : 3;
+    const int ns0 = (int)th_sel.size();
+    const int Kf = Kc_last;
+    ApplyCfg cfgq = cfg64;
+    cfgq.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, std::min(1e-7, std::max(1e-12, 0.3 * tol)));
+    int nsel = ns0;
+    DBuf<double> Xw((size_t)n * nsel);
+    {
+      DBuf<double> Yd((size_t)Kf * nsel);
+      NM_HIP(hipMemcpyAsync(Yd.p, Ysel.data(), 8 * (size_t)Kf * nsel, hipMemcpyHostToDevice, st));
+      bl.nn(n, Kf, nsel, 1.0, V.p, Kmax, Yd.p, Kf, 0.0, Xw.p, nsel);
+    }
+    // H11 = V_f^T A V_f (fixed over the passes)
+    DBuf<double> H11((size_t)Kf * Kf);
+    bl.tn(n, Kf, Kf, V.p, Kmax, AV.p, Kmax, H11.p);
+    std::vector<double> h11((size_t)Kf * Kf);
+    NM_HIP(hipMemcpyAsync(h11.data(), H11.p, 8 * h11.size(), hipMemcpyDeviceToHost, st));
+    NM_HIP(hipStreamSynchronize(st));
+    H11.release();
+    fw.ensure(P, bs);
+    for (int pass = 0; pass < npass; ++pass) {
+      const int q = nsel;
+      // low-pass q(t) = T_k((c_q - t) / e_q) / T_k((c_q - b) / e_q) with [c_q -+ e_q] = [lc, lmax]:
+      // positive and decreasing below lc, 1 at b, |q| <= delta on [lc, lmax].  The rounding
+      // noise is spread over the spectrum and weighed by lambda_j / lambda in the residual; to
+      // lower the floor r0 by f = tol / (10 r0), components above lc = lmax f^(2/3) are damped
+      // to delta = f / 3 (with a Weyl-law density the weighted noise below lc scales as
+      // (lc / lmax)^(3/2))
+      const double r0 = max_res();
+      const double f = std::min(0.5, std::max(1e-12, tol / (10.0 * r0)));
+      const double lc = std::min(std::max(2.0 * b, lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
+      const double tb = 1.0 + 2.0 * (lc - b) / (lmax - lc);
+      kq = std::max(2, (int)std::ceil(std::acosh(3.0 / f) / std::acosh(tb)));
+      std::vector<double> muq(kq + 1, 0.0);
+      muq[kq] = ((kq & 1) ? -1.0 : 1.0) / std::cosh(kq * std::acosh(tb));
+      const double cq = 0.5 * (lmax + lc), eq = 0.5 * (lmax - lc);
+      // Y = q(B) X, bs columns at a time
+      DBuf<double> Yq((size_t)n * q), MY((size_t)n * q), AY((size_t)n * q);
+      for (int j0 = 0; j0 < q; j0 += bs) {
+        const int nc = std::min(bs, q - j0);
+        NM_HIP(hipMemcpy2DAsync(T2.p, 8 * (size_t)nc, Xw.p + j0, 8 * (size_t)q, 8 * (size_t)nc, n,
+                                hipMemcpyDeviceToDevice, st));
+        filter_apply<double>(P, muq.data(), kq, cq, eq, 0.0, 0.0, nc, T2.p, W.p, cfgq, fw, st);
+        NM_HIP(hipMemcpy2DAsync(Yq.p + j0, 8 * (size_t)q, W.p, 8 * (size_t)nc, 8 * (size_t)nc, n,
+                                hipMemcpyDeviceToDevice, st));
+      }
+      refine_bapps += (int64_t)kq * q;
+      // M-orthogonalise against V_f (twice), then Cholesky QR (twice)
+      DBuf<double> Cq((size_t)Kf * q), Gq((size_t)q * q);
+      for (int it = 0; it < 2; ++it) {
+        mprod(Yq.p, MY.p, q);
+        bl.tn(n, Kf, q, V.p, Kmax, MY.p, q, Cq.p);
+        bl.nn(n, Kf, q, -1.0, V.p, Kmax, Cq.p, Kf, 1.0, Yq.p, q);
+      }
+      bool ok = true;
+      for (int it = 0; it < 2 && ok; ++it) {
+        mprod(Yq.p, MY.p, q);
+        bl.tn(n, q, q, Yq.p, q, MY.p, q, Gq.p);
+        std::vector<double> G((size_t)q * q), Ri;
+        NM_HIP(hipMemcpyAsync(G.data(), Gq.p, 8 * G.size(), hipMemcpyDeviceToHost, st));
+        NM_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < q; ++i)
+          for (int k = 0; k < i; ++k) G[i + (size_t)k * q] = G[k + (size_t)i * q] = 0.5 * (G[i + (size_t)k * q] + G[k + (size_t)i * q]);
+        chol_upper(q, G, ok);
+        if (!ok) break;
+        upper_inverse(q, G, Ri);
+        NM_HIP(hipMemcpyAsync(Gq.p, Ri.data(), 8 * Ri.size(), hipMemcpyHostToDevice, st));
+        bl.nn(n, q, q, 1.0, Yq.p, q, Gq.p, q, 0.0, MY.p, q);
+        std::swap(Yq.p, MY.p);
+      }
+      if (!ok) break;  // the refined vectors are (numerically) in the basis already
+      apply_op(P, NM_OP_A, q, Yq.p, AY.p, cfg64, st);
+      // Rayleigh-Ritz with (A, M) on [V_f, Y]
+      const int Kt = Kf + q;
+      DBuf<double> H12((size_t)Kf * q), H22((size_t)q * q);
+      bl.tn(n, Kf, q, V.p, Kmax, AY.p, q, H12.p);
+      bl.tn(n, q, q, Yq.p, q, AY.p, q, H22.p);
+      std::vector<double> h12((size_t)Kf * q), h22((size_t)q * q), Ht((size_t)Kt * Kt);
+      NM_HIP(hipMemcpyAsync(h12.data(), H12.p, 8 * h12.size(), hipMemcpyDeviceToHost, st));
+      NM_HIP(hipMemcpyAsync(h22.data(), H22.p, 8 * h22.size(), hipMemcpyDeviceToHost, st));
+      NM_HIP(hipStreamSynchronize(st));
+      for (int jj = 0; jj < Kf; ++jj)
+        for (int i = 0; i < Kf; ++i)
+          Ht[i + (size_t)jj * Kt] = 0.5 * (h11[i + (size_t)jj * Kf] + h11[jj + (size_t)i * Kf]);
+      for (int jj = 0; jj < q; ++jj)
+        for (int i = 0; i < Kf; ++i)
+          Ht[i + (size_t)(Kf + jj) * Kt] = Ht[(Kf + jj) + (size_t)i * Kt] = h12[i + (size_t)jj * Kf];
+      for (int jj = 0; jj < q; ++jj)
+        for (int i = 0; i < q; ++i)
+          Ht[(Kf + i) + (size_t)(Kf + jj) * Kt] = 0.5 * (h22[i + (size_t)jj * q] + h22[jj + (size_t)i * q]);
+      std::vector<double> tht, Zt;
+      sym_eig(Kt, Ht, tht, Zt);
+      std::vector<int> cand;
+      for (int i = 0; i < Kt; ++i)
+        if (tht[i] >= a && tht[i] <= b) cand.push_back(i);
+      const int nc = (int)cand.size();
+      if (nc == 0) break;
+      std::vector<double> zv((size_t)Kf * nc), zy((size_t)q * nc), thc(nc);
+      for (int k = 0; k < nc; ++k) {
+        const double* zc = Zt.data() + (size_t)cand[k] * Kt;
+        std::copy(zc, zc + Kf, zv.begin() + (size_t)k * Kf);
+        std::copy(zc + Kf, zc + Kt, zy.begin() + (size_t)k * q);
+        thc[k] = tht[cand[k]];
+      }
+      DBuf<double> zvd((size_t)Kf * nc), zyd((size_t)q * nc), Xc((size_t)n * nc), AXc((size_t)n * nc),
+          MXc((size_t)n * nc), thd(nc), rn(nc), mn(nc);
+      NM_HIP(hipMemcpyAsync(zvd.p, zv.data(), 8 * zv.size(), hipMemcpyHostToDevice, st));
+      NM_HIP(hipMemcpyAsync(zyd.p, zy.data(), 8 * zy.size(), hipMemcpyHostToDevice, st));
+      NM_HIP(hipMemcpyAsync(thd.p, thc.data(), 8 * nc, hipMemcpyHostToDevice, st));
+      bl.nn(n, Kf, nc, 1.0, V.p, Kmax, zvd.p, Kf, 0.0, Xc.p, nc);
+      bl.nn(n, q, nc, 1.0, Yq.p, q, zyd.p, q, 1.0, Xc.p, nc);
+      bl.nn(n, Kf, nc, 1.0, AV.p, Kmax, zvd.p, Kf, 0.0, AXc.p, nc);
+      bl.nn(n, q, nc, 1.0, AY.p, q, zyd.p, q, 1.0, AXc.p, nc);
+      mprod(Xc.p, MXc.p, nc);
+      hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n * nc)), dim3(256), 0, st, n, nc, AXc.p, MXc.p, thd.p,
+                         AXc.p);
+      col_dots(n, nc, AXc.p, nc, AXc.p, nc, rn.p, st);
+      col_dots(n, nc, MXc.p, nc, MXc.p, nc, mn.p, st);
+      std::vector<double> r2(nc), m2(nc), rc(nc);
+      NM_HIP(hipMemcpy(r2.data(), rn.p, 8 * nc, hipMemcpyDeviceToHost));
+      NM_HIP(hipMemcpy(m2.data(), mn.p, 8 * nc, hipMemcpyDeviceToHost));
+      for (int k = 0; k < nc; ++k) rc[k] = std::sqrt(r2[k]) / (std::fabs(thc[k]) * std::sqrt(m2[k]));
+      // keep the ns0 candidates of smallest residual (window combinations of unconverged
+      // directions have residuals orders of magnitude above the refined pairs), ascending
+      std::vector<int> ord(nc);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::sort(ord.begin(), ord.end(), [&](int x, int y) { return rc[x] < rc[y]; });
+      ord.resize(std::min(nc, ns0));
+      std::sort(ord.begin(), ord.end());
+      nsel = (int)ord.size();
+      DBuf<double> Xn((size_t)n * nsel);
+      th_sel.assign(nsel, 0.0);
+      res_sel.assign(nsel, 0.0);
+      bool all_ok = true;
+      for (int k = 0; k < nsel; ++k) {
+        th_sel[k] = thc[ord[k]];
+        res_sel[k] = rc[ord[k]];
+        all_ok = all_ok && res_sel[k] <= tol;
+        NM_HIP(hipMemcpy2DAsync(Xn.p + k, 8 * (size_t)nsel, Xc.p + ord[k], 8 * (size_t)nc, 8, n,
+                                hipMemcpyDeviceToDevice, st));
+      }
+      Xw = std::move(Xn);
+      ++refine_passes;
+      if (o.verbose)
+        fprintf(stderr, "[nmodes] refine pass %d degree %d pairs %d resid-max %.2e t=%.2fs\n", pass, kq, nsel,
+                max_res(), clock.s());
+      if (all_ok || max_res() > 0.5 * r0) break;
+    }
+    if (refine_passes > 0) Xref = std::move(Xw);
+  }
+  const double refine_seconds = refine_passes > 0 ? rclock.s() : 0.0;
 
   // ---------------- result: the min(nev, count) smallest pairs in the window
   const int ns = (int)th_sel.size();
@@ -615,12 +815,18 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     r->resid[i] = res_sel[i];
   }
   if (cnt > 0) {
-    DBuf<double> Yd((size_t)Kc_last * cnt), sg(cnt);
-    NM_HIP(hipMemcpyAsync(Yd.p, Ysel.data(), 8 * (size_t)Kc_last * cnt, hipMemcpyHostToDevice, st));
+    DBuf<double> sg(cnt);
     NM_HIP(hipMalloc((void**)&r->X, 8 * (size_t)n * cnt));
     // Ritz vectors in the internal node order, then to the canonical order
     DBuf<double> Xi((size_t)n * cnt);
-    bl.nn(n, Kc_last, cnt, 1.0, V.p, Kmax, Yd.p, Kc_last, 0.0, Xi.p, cnt);
+    if (refine_passes > 0) {
+      NM_HIP(hipMemcpy2DAsync(Xi.p, 8 * (size_t)cnt, Xref.p, 8 * (size_t)ns, 8 * (size_t)cnt, n,
+                              hipMemcpyDeviceToDevice, st));
+    } else {
+      DBuf<double> Yd((size_t)Kc_last * cnt);
+      NM_HIP(hipMemcpyAsync(Yd.p, Ysel.data(), 8 * (size_t)Kc_last * cnt, hipMemcpyHostToDevice, st));
+      bl.nn(n, Kc_last, cnt, 1.0, V.p, Kmax, Yd.p, Kc_last, 0.0, Xi.p, cnt);
+    }
     permute_rows(N, 3 * cnt, Xi.p, r->X, P->perm.p, 8, st);
     hipLaunchKernelGGL(k_col_sign, dim3(cnt), dim3(256), 0, st, n, cnt, r->X, sg.p);
     hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(n * cnt)), dim3(256), 0, st, n, cnt, sg.p, r->X);
@@ -644,6 +850,10 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     const double sz = prec ? 4.0 : 8.0;
     r->hot_bytes = (double)P->nnzb * (4.0 + sz) + 4.0 * (P->N + 1) + sz * P->N + 4.0 * n * bs * sz;
   }
+  r->refine_passes = refine_passes;
+  r->refine_degree = kq;
+  r->refine_seconds = refine_seconds;
+  r->refine_bapps = refine_bapps;
   r->seconds = clock.s();
   *out = r;
   if (!converged || nconv < cnt) throw Error(NM_PARTIAL, "solve did not converge all pairs in the window");

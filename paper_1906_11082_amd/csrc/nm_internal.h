@@ -123,7 +123,7 @@ struct nm_pencil {
   int grp_rows = 0;
   nm::DBuf<int32_t> grp_ptr, grp_col;
   nm::DBuf<double> grp_coef;
-  int grouped = 1;  // 0 forces the per-row kernels
+  int grouped = 1;  // 0: per-row kernels only; 1: grouped from 32 columns on; 2: grouped at any width
   rocblas_handle blas = nullptr;
   void ensure_fp32(hipStream_t st);
 };

@@ -42,6 +42,10 @@ __device__ __forceinline__ Vx<T, V> ldv(const T* __restrict__ p) {
   } else if constexpr (std::is_same<T, float>::value && V == 2) {
     float2 q = *reinterpret_cast<const float2*>(p);
     r.v[0] = q.x; r.v[1] = q.y;
+  } else if constexpr (std::is_same<T, double>::value) {
+    static_assert(V == 4, "double rows are read 1, 2 or 4 at a time");
+    double2 q = *reinterpret_cast<const double2*>(p), t = *reinterpret_cast<const double2*>(p + 2);
+    r.v[0] = q.x; r.v[1] = q.y; r.v[2] = t.x; r.v[3] = t.y;
   } else {
     float4 q = *reinterpret_cast<const float4*>(p);
     r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
@@ -56,9 +60,28 @@ __device__ __forceinline__ void stv(T* __restrict__ p, const Vx<T, V>& r) {
     *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
   } else if constexpr (std::is_same<T, float>::value && V == 2) {
     *reinterpret_cast<float2*>(p) = make_float2(r.v[0], r.v[1]);
+  } else if constexpr (std::is_same<T, double>::value) {
+    static_assert(V == 4, "double rows are written 1, 2 or 4 at a time");
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(r.v[2], r.v[3]);
   } else {
     *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
   }
+}
+
+// streaming (nontemporal) variants for operands read or written once per
+// step, so they do not displace the gathered rows from L2
+template <class T, int V>
+__device__ __forceinline__ Vx<T, V> ldv_nt(const T* __restrict__ p) {
+  Vx<T, V> r;
+#pragma unroll
+  for (int i = 0; i < V; ++i) r.v[i] = __builtin_nontemporal_load(p + i);
+  return r;
+}
+template <class T, int V>
+__device__ __forceinline__ void stv_nt(T* __restrict__ p, const Vx<T, V>& r) {
+#pragma unroll
+  for (int i = 0; i < V; ++i) __builtin_nontemporal_store(r.v[i], p + i);
 }
 
 // LDS staging of the CSR entries of the rows a workgroup touches: the
@@ -96,28 +119,33 @@ __device__ __forceinline__ Stage<T, NV> stage_rows(const int32_t* __restrict__ r
 // (or global memory when the rows did not fit): 8 gathers in flight per lane
 // cl / vl point at the first staged entry (entry index `base`) or at the
 // global arrays (base 0); entries are read at cl[k - base], so no pointer
-// outside an allocation is ever formed.
-template <class T, int V>
+// outside an allocation is ever formed.  Callers pass the LDS arrays and the
+// global arrays in separate calls, so that after inlining the compiler knows
+// each pointer's address space: LDS reads become ds_read (not flat loads,
+// which would occupy the texture-address unit that the gathers saturate).
+template <class T, int V, int U = 8>
 __device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int32_t base, int32_t k0, int32_t k1,
                                              const T* __restrict__ X, uint32_t w, uint32_t e) {
   Vx<T, V> acc;
 #pragma unroll
   for (int i = 0; i < V; ++i) acc.v[i] = T(0);
-  for (int32_t k = k0; k < k1; k += 8) {
-    uint32_t c[8];
-    T a[8];
+  for (int32_t k = k0; k < k1; k += U) {
+    uint32_t c[U];
+    T a[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
+      // past the row end: re-read the first entry (always valid) with weight 0
       const bool in = k + u < k1;
       const int32_t kk = (in ? k + u : k0) - base;
       c[u] = (uint32_t)cl[kk];
-      a[u] = in ? vl[kk] : T(0);
+      const T av = vl[kk];
+      a[u] = in ? av : T(0);
     }
-    Vx<T, V> x[8];
+    Vx<T, V> x[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
+    for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int i = 0; i < V; ++i) acc.v[i] += a[u] * x[u].v[i];
   }
@@ -126,6 +154,44 @@ __device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int
 
 // flat index of this lane in a launch covering rows * (w / V) lanes
 __device__ __forceinline__ uint32_t lane_id() { return (uint32_t)nm_xcd_block() * blockDim.x + threadIdx.x; }
+
+// sum over the row's 3x3 blocks of (block row c) . X[col] (3 gathered V-vectors
+// per block); cl / vl as in row_spmv (LDS or global arrays, entry k at k - base)
+template <class T, int V>
+__device__ __forceinline__ Vx<T, V> ag_row(const int32_t* cl, const T* vl, int32_t base, int32_t k0, int32_t k1,
+                                           const T* __restrict__ X, uint32_t w, uint32_t b, uint32_t c,
+                                           uint32_t v) {
+  Vx<T, V> acc;
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+  for (int32_t k = k0; k < k1; k += 4) {
+    uint32_t cc[4];
+    T a[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = k + u < k1;
+      const int32_t kk = (in ? k + u : k0) - base;
+      cc[u] = (uint32_t)cl[kk];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T av = vl[9 * (size_t)kk + 3 * c + d];
+        a[u][d] = in ? av : T(0);
+      }
+    }
+    Vx<T, V> x[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[u][d] = ldv<T, V>(X + (size_t)(cc[u] * w + d * b + v));
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] += a[u][d] * x[u][d].v[i];
+  }
+  return acc;
+}
 
 // F = A_G X [+ E_G S] ; optionally Y1 = D^{-1} F / theta (first Chebyshev iterate).
 // Lane (row, c, column group of V): 3 block entries and 3 gathered V-vectors per nonzero block.
@@ -156,36 +222,9 @@ __global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const 
   const uint32_t row = g / wl;
   const uint32_t e = (g - row * wl) * V;
   const uint32_t c = e / b, v = e - c * b;
-  const int32_t* cl = staged ? s_col : col;
-  const T* vl = staged ? s_val : ag;
-  const int32_t base = staged ? kb : 0;
-  Vx<T, V> acc;
-#pragma unroll
-  for (int i = 0; i < V; ++i) acc.v[i] = T(0);
   const int32_t k0 = rp[row], k1 = rp[row + 1];
-  for (int32_t k = k0; k < k1; k += 4) {
-    uint32_t cc[4];
-    T a[4][3];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool in = k + u < k1;
-      const int32_t kk = (in ? k + u : k0) - base;
-      cc[u] = (uint32_t)cl[kk];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) a[u][d] = in ? vl[9 * (size_t)kk + 3 * c + d] : T(0);
-    }
-    Vx<T, V> x[4][3];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) x[u][d] = ldv<T, V>(X + (size_t)(cc[u] * w + d * b + v));
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc.v[i] += a[u][d] * x[u][d].v[i];
-  }
+  Vx<T, V> acc = staged ? ag_row<T, V>(s_col, s_val, kb, k0, k1, X, w, b, c, v)
+                        : ag_row<T, V>(col, ag, 0, k0, k1, X, w, b, c, v);
   if (S) {
     for (int32_t q = egp[row]; q < egp[row + 1]; ++q) {
       const T ev = egv[3 * (size_t)q + c];
@@ -252,9 +291,9 @@ __global__ __launch_bounds__(256) void k_spmm_scalar(uint32_t rows, uint32_t w, 
   auto sg = stage_rows<T, 1>(rp, col, val, rows, wl, s_col, s_val);
   if (g >= rows * wl) return;
   const uint32_t row = g / wl, e = (g - row * wl) * V;
-  const int32_t* cl = sg.ok ? s_col : col;
-  const T* vl = sg.ok ? s_val : val;
-  Vx<T, V> acc = row_spmv<T, V>(cl, vl, sg.ok ? sg.kbeg : 0, rp[row], rp[row + 1], X, w, e);
+  const int32_t k0 = rp[row], k1 = rp[row + 1];
+  const Vx<T, V> acc = sg.ok ? row_spmv<T, V>(s_col, s_val, sg.kbeg, k0, k1, X, w, e)
+                             : row_spmv<T, V>(col, val, 0, k0, k1, X, w, e);
   stv<T, V>(Y + (size_t)row * w + e, acc);
 }
 
@@ -320,24 +359,24 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
   const size_t o = (size_t)row * w + e;
   // own-row operands first, so their latency overlaps the gathers
   const Vx<T, V> yc = ldv<T, V>(ycur + o);
-  const Vx<T, V> ff = ldv<T, V>(f + o);
+  const Vx<T, V> ff = ldv_nt<T, V>(f + o);
   Vx<T, V> yp;
   if (prev_zero) {
 #pragma unroll
     for (int i = 0; i < V; ++i) yp.v[i] = T(0);
   } else {
-    yp = ldv<T, V>(yprev + o);
+    yp = ldv_nt<T, V>(yprev + o);
   }
   const T dr = dinv[row];
-  const int32_t* cl = sg.ok ? s_col : col;
-  const T* vl = sg.ok ? s_val : val;
-  Vx<T, V> s = row_spmv<T, V>(cl, vl, sg.ok ? sg.kbeg : 0, rp[row], rp[row + 1], ycur, w, e);
+  const int32_t k0 = rp[row], k1 = rp[row + 1];
+  const Vx<T, V> s = sg.ok ? row_spmv<T, V>(s_col, s_val, sg.kbeg, k0, k1, ycur, w, e)
+                           : row_spmv<T, V>(col, val, 0, k0, k1, ycur, w, e);
   const T bd = beta * dr;
   Vx<T, V> z;
 #pragma unroll
   for (int i = 0; i < V; ++i) z.v[i] = yc.v[i] + alpha * (yc.v[i] - yp.v[i]) + bd * (ff.v[i] - s.v[i]);
   if (mode == 0) {
-    stv<T, V>(out + o, z);
+    stv_nt<T, V>(out + o, z);
     return;
   }
   const Vx<T, V> wi = ldv<T, V>(win + o);
@@ -364,22 +403,65 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
 }
 
 
+// sum over the group's union columns of coef[., r] X[col] for the R rows;
+// cl / cf as in row_spmv (LDS or global arrays, entry l at l - base)
+template <class T, int V, int R>
+__device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_t base, int32_t l0, int32_t l1,
+                                          const T* __restrict__ X, uint32_t w, uint32_t e, Vx<T, V> (&acc)[R]) {
+  for (int32_t l = l0; l < l1; l += 4) {
+    uint32_t c[4];
+    bool in[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      in[u] = l + u < l1;
+      c[u] = (uint32_t)cl[(in[u] ? l + u : l0) - base];
+    }
+    Vx<T, V> x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T* a = cf + (size_t)((in[u] ? l + u : l0) - base) * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T ar = in[u] ? a[r] : T(0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[r].v[i] += ar * x[u].v[i];
+      }
+    }
+  }
+}
+
 // Row-group Chebyshev-Jacobi step (same arithmetic and modes as k_cj_step).
 // Rows are processed in groups of R consecutive rows of the Morton order;
 // each lane owns one V-wide entry slot of all R rows and walks the union of
 // their columns once, with an R-wide coefficient row per union column
 // (zeros where a row lacks the column).  A gathered neighbour row serves
-// every row of the group that touches it, so the gather volume (the
-// bottleneck: L2 -> CU traffic) drops by |sum of row lengths| / |union|.
+// every row of the group that touches it, so the number of gathers (which
+// bound the step through the texture-address unit) drops by the ratio of
+// the rows' entries to the size of their union.  Union columns and
+// coefficients of the workgroup's groups are staged in LDS.
 template <class T, int V, int R>
 __global__ __launch_bounds__(256) void k_cj_group(
     uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
     const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
     const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
     T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc) {
+  constexpr int GCAP = 640;
+  __shared__ int32_t s_col[GCAP];
+  __shared__ T s_cf[GCAP * R];
   const uint32_t wl = w / V;
   const uint32_t ngroups = (N + R - 1) / R;
   const uint32_t g = lane_id();
+  const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
+  const uint32_t G0 = min(g0 / wl, ngroups - 1), G1 = min((g0 + blockDim.x - 1) / wl, ngroups - 1);
+  const int32_t lb = gptr[G0], le = gptr[G1 + 1];
+  const bool staged = le - lb <= GCAP;
+  if (staged) {
+    for (int32_t i = threadIdx.x; i < le - lb; i += blockDim.x) s_col[i] = gcol[lb + i];
+    for (int32_t i = threadIdx.x; i < (le - lb) * R; i += blockDim.x) s_cf[i] = gcoef[(size_t)lb * R + i];
+  }
+  __syncthreads();
   if (g >= ngroups * wl) return;
   const uint32_t grp = g / wl, e = (g - grp * wl) * V;
   const uint32_t r0 = grp * R;
@@ -389,49 +471,30 @@ __global__ __launch_bounds__(256) void k_cj_group(
 #pragma unroll
     for (int i = 0; i < V; ++i) acc[r].v[i] = T(0);
   const int32_t l0 = gptr[grp], l1 = gptr[grp + 1];
-  for (int32_t l = l0; l < l1; l += 4) {
-    uint32_t c[4];
-    bool in[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      in[u] = l + u < l1;
-      c[u] = (uint32_t)gcol[in[u] ? l + u : l0];
-    }
-    Vx<T, V> x[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = ldv<T, V>(ycur + (size_t)(c[u] * w + e));
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!in[u]) continue;
-      const T* cf = gcoef + (size_t)(l + u) * R;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const T a = cf[r];
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc[r].v[i] += a * x[u].v[i];
-      }
-    }
-  }
+  if (staged)
+    group_sum<T, V, R>(s_col, s_cf, lb, l0, l1, ycur, w, e, acc);
+  else
+    group_sum<T, V, R>(gcol, gcoef, 0, l0, l1, ycur, w, e, acc);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t row = r0 + r;
     if (row >= N) break;
     const size_t o = (size_t)row * w + e;
     const Vx<T, V> yc = ldv<T, V>(ycur + o);
-    const Vx<T, V> ff = ldv<T, V>(f + o);
+    const Vx<T, V> ff = ldv_nt<T, V>(f + o);
     Vx<T, V> yp;
     if (prev_zero) {
 #pragma unroll
       for (int i = 0; i < V; ++i) yp.v[i] = T(0);
     } else {
-      yp = ldv<T, V>(yprev + o);
+      yp = ldv_nt<T, V>(yprev + o);
     }
     const T bd = beta * dinv[row];
     Vx<T, V> z;
 #pragma unroll
     for (int i = 0; i < V; ++i) z.v[i] = yc.v[i] + alpha * (yc.v[i] - yp.v[i]) + bd * (ff.v[i] - acc[r].v[i]);
     if (mode == 0) {
-      stv<T, V>(out + o, z);
+      stv_nt<T, V>(out + o, z);
       continue;
     }
     const Vx<T, V> wi = ldv<T, V>(win + o);
@@ -537,11 +600,14 @@ struct GroupPlan {
   const int32_t *gptr = nullptr, *gcol = nullptr;
   const void* gcoef = nullptr;
 };
-// FP64 only: in FP32 the per-row kernel measured as fast or faster.
+// FP64 only (in FP32 the per-row kernel measured as fast), and by default
+// only from 32 columns on: narrower blocks put more groups in a workgroup than
+// its LDS stage holds.  grouped == 2 forces the grouped kernel at any width.
 template <class T>
 GroupPlan group_plan(const nm_pencil* P, int b) {
   GroupPlan tp;
-  if (sizeof(T) != 8 || !P->grouped || P->grp_rows <= 0 || b < 2) return tp;
+  if (sizeof(T) != 8 || !P->grouped || P->grp_rows <= 0 || b < 1) return tp;
+  if (P->grouped == 1 && b < 32) return tp;
   tp.on = true;
   tp.R = P->grp_rows;
   tp.gptr = P->grp_ptr.p;

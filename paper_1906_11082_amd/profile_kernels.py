@@ -6,10 +6,11 @@
 
 Launches, on the three-layer planet at n_half (default 20): `reps` M-solves
 of `steps` Chebyshev-Jacobi steps on a block of `block` columns (so the
-middle step kernel k_cj_step dominates), one filter application of degree
-`degree`, and a plain device copy of `copy_mb` MB (torch) that calibrates
-the HBM byte counters.  Prints the algorithmic bytes of one middle
-k_cj_step launch so the counters can be compared with it.
+middle-step kernel dominates: k_cj_group for FP64 blocks of 32 columns or
+more, k_cj_step otherwise), one filter application of degree `degree`, and a
+plain device copy of `copy_mb` MB (torch) that calibrates the HBM byte
+counters.  Prints the algorithmic bytes of one middle-step launch so the
+counters can be compared with it.
 """
 import argparse
 import os
@@ -55,7 +56,7 @@ def main():
     torch.cuda.synchronize()
     nnzb, N, n = P.info["nnzb"], P.info["n_node"], P.info["n_disp"]
     cj = nnzb * (4 + s) + 4 * (N + 1) + s * N + 4 * n * args.block * s
-    print("k_cj_step algorithmic bytes per launch %d (nnzb %d, N %d, block %d, %s)"
+    print("Chebyshev-Jacobi step algorithmic bytes per launch %d (nnzb %d, N %d, block %d, %s)"
           % (cj, nnzb, N, args.block, args.precision))
     print("copy kernel bytes per launch %d (read) + %d (write)" % (n_copy * 8, n_copy * 8))
 

@@ -189,7 +189,7 @@ def test_row_group_kernel_matches_per_row(torch_cuda, ncols, monkeypatch):
     import paper_1906_11082_amd as nm
     d = dict(make_planet("three_layer_planet", n_half=5, order=2, pres_order=1))
     pens = {}
-    for tag, on, R in (("row", "0", "4"), ("g4", "1", "4"), ("g8", "1", "8")):
+    for tag, on, R in (("row", "0", "4"), ("g4", "2", "4"), ("g8", "2", "8")):
         monkeypatch.setenv("NM_ROW_GROUPS", on)
         monkeypatch.setenv("NM_GROUP_ROWS", R)
         pens[tag] = nm.Pencil(d)

@@ -89,16 +89,48 @@ def test_layered_cowling_matches_shift_invert():
     assert r.resid.max() <= 1e-9
 
 
-def test_fp32_filter_same_eigenvalues():
-    """FP32 filter + FP64 Rayleigh-Ritz reaches the FP64 eigenvalues."""
+def test_fp32_filter_refined_to_fp64_accuracy():
+    """FP32 filter (values, vectors, accumulation) + FP64 Lanczos, Rayleigh-Ritz
+    and low-pass refinement: residual <= 1e-8 and eigenvalues within 1e-8
+    relative of the FP64 solve; without the refinement the FP32 residual
+    floor is higher."""
     import paper_1906_11082_amd as nm
     d = make_planet("homogeneous_ball", n_half=4, order=1)
     G = nm.Pencil(d)
     r64 = G.filtered_eig(0.5, 40.0, 30, 1e-10, degree=40, block=8)
-    r32 = G.filtered_eig(0.5, 40.0, 30, 1e-6, degree=40, block=8, precision=1, allow_partial=True)
-    n = min(r32.count, 30)
-    print("fp32 resid max %.2e" % r32.resid.max(), flush=True)
-    assert np.abs(r32.lam[:n] - r64.lam[:n]).max() <= 1e-8 * r64.lam[:n].max()
+    r32 = G.filtered_eig(0.5, 40.0, 30, 1e-8, degree=40, block=8, precision=1)
+    print("fp32 refined: resid max %.2e passes %d degree %d" % (r32.resid.max(), r32.stats["refine_passes"],
+                                                               r32.stats["refine_degree"]), flush=True)
+    assert r32.count == 30 and r32.stats["refine_passes"] >= 1
+    assert r32.resid.max() <= 1e-8
+    assert np.abs(r32.lam - r64.lam).max() <= 1e-8 * r64.lam.max()
+    O = OPencil(d)
+    X32, X64 = r32.X.cpu().numpy(), r64.X.cpu().numpy()
+    for g in _clusters(r64.lam):
+        if g[-1] == 29:
+            continue
+        sv = np.linalg.svd(X32[:, g].T @ (O.M @ X64[:, g]), compute_uv=False)
+        assert sv.min() > 1 - 1e-6, (g, sv)
+    raw = G.filtered_eig(0.5, 40.0, 30, 1e-8, degree=40, block=8, precision=1, refine=-1, allow_partial=True)
+    print("fp32 unrefined: resid max %.2e" % raw.resid.max(), flush=True)
+    assert raw.stats["refine_passes"] == 0 and raw.resid.max() > r32.resid.max()
+
+
+def test_fp32_layered_cowling_refined():
+    """Three-layer planet, P2/P1, Cowling: the FP32-filter path with FP64
+    refinement finds all pairs in [1, 12] within 1e-8 relative of the exact-Schur
+    shift-invert reference, residuals <= 1e-8."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    print("\n[case] layered P2/P1 n_half=4 FP32 filter", flush=True)
+    G = nm.Pencil(d)
+    r = G.filtered_eig(1.0, 12.0, 200, 1e-8, block=8, precision=1, verbose=1)
+    O = OPencil(d)
+    lam, _ = _cowling_reference(O, 6.0, min(3 * max(r.count, 10), 80))
+    ref = lam[(lam >= 1.0) & (lam <= 12.0)]
+    assert r.count == len(ref) and r.count > 0
+    assert np.abs(r.lam - ref).max() <= 1e-8 * ref.max()
+    assert r.resid.max() <= 1e-8
 
 
 def test_rotation_projection_matches_oracle():
