@@ -157,6 +157,8 @@ def main():
             "column_bapps": st["bapps"], "pairs": last.count, "resid_max": float(last.resid.max()) if last.count else None,
             "lmax": st["lmax"], "solve_seconds": st["seconds"], "filter_seconds": st["filter_seconds"],
             "partial": bool(last.partial),
+            "refine_passes": st["refine_passes"], "refine_degree": st["refine_degree"],
+            "refine_seconds": st["refine_seconds"], "refine_column_bapps": st["refine_bapps"],
         },
         "roofline": {
             "bound": "hbm",

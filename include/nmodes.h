@@ -208,6 +208,16 @@ nm_status nm_pencil_nodes(const nm_pencil* p, int64_t* node_geom, int64_t* pres_
 nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const void* X, void* Y,
                           const nm_apply_opts* opts, void* stream);
 
+/* Autotuning of the mass-solve step (the hot loop of every filter step) on
+ * this pencil: times middle Chebyshev-Jacobi steps for block widths 8, 16,
+ * 32 and 64 and, in FP64, the per-row and row-group kernels, then keeps the
+ * fastest per column: nm_filtered_eig with block 0 uses that width (at most
+ * nev / 4, rounded down to a multiple of 8, at least 8) and every
+ * later mass solve that kernel choice.  Allocates 3 x 64 columns of work
+ * vectors for the duration of the call.  block / us_per_column (may be NULL):
+ * the winner and its time per column and step in microseconds. */
+nm_status nm_pencil_autotune(nm_pencil* p, int32_t precision, void* stream, int32_t* block, double* us_per_column);
+
 /* Jackson-damped Chebyshev coefficients mu[0..m] of the indicator of [a, b]
  * after mapping [lmin, lmax] onto [-1, 1] (the polynomial filter). */
 nm_status nm_filter_coeffs(double a, double b, double lmin, double lmax, int32_t m, double* mu);
@@ -241,13 +251,77 @@ nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, v
  * vectors and accumulation: eps32) leaves the window residuals at a floor
  * near eps * lambda_max / lambda.  The Lanczos therefore stops when they are
  * below tol or no longer improve, and the window pairs are refined in FP64:
- * each pass applies a Chebyshev low-pass polynomial (1 at b, small beyond a
- * cut-off chosen from the current floor) to them and runs Rayleigh-Ritz on
- * (A, M) over the Krylov basis together with the refined vectors.  NM_PARTIAL:
+ * each pass applies (B / b) q(B), q a Chebyshev low-pass polynomial (1 at b,
+ * small beyond a cut-off chosen from the floor), to the window Ritz vectors
+ * and to those just above the window, and runs Rayleigh-Ritz on (A, M) over
+ * the refined vectors.  NM_PARTIAL:
  * the pairs returned are those found, some with residual above tol, or the
  * basis cap was reached first. */
 nm_status nm_filtered_eig(const nm_pencil* p, double a, double b, int32_t nev, double tol,
                           const nm_eig_opts* opts, nm_eig_result** out);
+
+/* Several windows [a[i], b[i]] of one pencil (spectrum slicing, Sec. 6.1),
+ * nev[i] pairs each, solved together: one block Lanczos per window, each in
+ * its own host thread and HIP stream, with their filter applications batched
+ * into one block of concatenated columns (one Chebyshev series per column,
+ * zero-padded to the largest degree), so the matrices are streamed once per
+ * step for all windows.  A window's result is the one nm_filtered_eig gives
+ * for it with the same bounds and seed.  All windows use one filter interval
+ * (opts->lmin/lmax, or estimated once) and opts otherwise as
+ * nm_filtered_eig; the null factor (null_filter 1) is not allowed.  out:
+ * caller array of nslices (1..64) result pointers, each freed with
+ * nm_result_free; NM_PARTIAL if any window is partial (all results set); on
+ * an error no result is returned. */
+nm_status nm_filtered_eig_slices(const nm_pencil* p, int32_t nslices, const double* a, const double* b,
+                                 const int32_t* nev, double tol, const nm_eig_opts* opts, nm_eig_result** out);
+
+/* ---- Request server (continuous batching of solves on one GPU) ----
+ * Requests (a planet, its windows and options) are admitted in arrival order
+ * while the sum of their estimated device memory stays within the budget and
+ * at most max_active run at once; each admitted request runs on its own host
+ * thread and HIP stream (assembly, then nm_filtered_eig_slices over its
+ * windows, then optionally nm_project_rotation over their union), so requests
+ * that arrive while others run overlap with them on the device.  A request's
+ * results are those it gives alone.  The memory estimate is made from the
+ * mesh sizes before assembly (node count from vertices, tets and order;
+ * matrices, assembly staging, Krylov bases and work blocks per window). */
+typedef struct nm_server nm_server;
+
+typedef struct {
+  nm_mesh mesh;          /* borrowed during nm_server_submit only (copied) */
+  nm_material material;  /* borrowed during nm_server_submit only (copied) */
+  double omega[3];       /* rotation vector */
+  int32_t nslices;       /* windows, 1..64 */
+  const double* a;       /* host [nslices] lower ends (copied) */
+  const double* b;       /* host [nslices] upper ends (copied) */
+  const int32_t* nev;    /* host [nslices] (copied) */
+  double tol;            /* residual bound */
+  nm_eig_opts opts;      /* as for nm_filtered_eig; opts.stream is ignored */
+  int32_t rotate;        /* 1: also project the Coriolis term over the union of the windows */
+} nm_request;
+
+typedef struct {
+  int32_t status;            /* nm_status of the request (NM_PARTIAL: some pairs above tol) */
+  char error[256];           /* message when status < 0 */
+  int32_t nslices;
+  nm_eig_result** slices;    /* [nslices] results (NULL entries on error) */
+  nm_rot_result* rotation;   /* NULL unless requested and found */
+  double t_submit, t_start, t_end;  /* seconds since nm_server_create */
+  double est_bytes;          /* the admission estimate */
+} nm_server_result;
+
+/* max_active >= 1; the server admits the first queued request whenever
+ * nothing runs, whatever its estimate. */
+nm_status nm_server_create(double hbm_budget_bytes, int32_t max_active, nm_server** out);
+/* Queue a request; *ticket identifies it for nm_server_wait. */
+nm_status nm_server_submit(nm_server* s, const nm_request* req, int64_t* ticket);
+/* Block until the request has finished; *out is freed with nm_server_result_free.
+ * Each ticket can be waited for once. */
+nm_status nm_server_wait(nm_server* s, int64_t ticket, nm_server_result** out);
+void nm_server_result_free(nm_server_result* r);
+/* Run every queued request to completion, then free the server (results not
+ * waited for are discarded). */
+nm_status nm_server_destroy(nm_server* s);
 
 /* Rotating modes by projection on the non-rotating eigenvectors of basis
  * (Sec. 7, eqs. "linearpb", "sublinear0"): keeps omega > 0 with omega^2 in

@@ -25,7 +25,9 @@ MAT_AG, MAT_M, MAT_R, MAT_KP, MAT_EG = range(5)
 OP_AG, OP_M, OP_R, OP_KP, OP_EG, OP_EGT, OP_KPINV, OP_A, OP_MINV, OP_B = range(10)
 
 EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pencil_nodes", "nm_pencil_apply",
-            "nm_filter_coeffs", "nm_filter_degree", "nm_filter_apply", "nm_spectrum_bounds", "nm_filtered_eig", "nm_project_rotation",
+            "nm_filter_coeffs", "nm_filter_degree", "nm_filter_apply", "nm_spectrum_bounds", "nm_filtered_eig",
+            "nm_filtered_eig_slices", "nm_project_rotation", "nm_pencil_autotune", "nm_server_create",
+            "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
             "nm_pencil_free", "nm_last_error", "nm_version"]
 
@@ -80,6 +82,19 @@ class _RotResult(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class _Request(C.Structure):
+    _fields_ = [("mesh", _Mesh), ("material", _Material), ("omega", C.c_double * 3), ("nslices", C.c_int32),
+                ("a", C.c_void_p), ("b", C.c_void_p), ("nev", C.c_void_p), ("tol", C.c_double),
+                ("opts", _EigOpts), ("rotate", C.c_int32)]
+
+
+class _ServerResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("error", C.c_char * 256), ("nslices", C.c_int32),
+                ("slices", C.POINTER(C.POINTER(_EigResult))), ("rotation", C.POINTER(_RotResult)),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double),
+                ("est_bytes", C.c_double)]
+
+
 _lib = None
 
 
@@ -111,6 +126,14 @@ def load_library(path: str | None = None):
                                C.c_int32),
         "nm_filtered_eig": ([P, C.c_double, C.c_double, C.c_int32, C.c_double, C.POINTER(_EigOpts),
                              C.POINTER(C.POINTER(_EigResult))], C.c_int32),
+        "nm_pencil_autotune": ([P, C.c_int32, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int32),
+        "nm_server_create": ([C.c_double, C.c_int32, C.POINTER(C.c_void_p)], C.c_int32),
+        "nm_server_submit": ([P, C.POINTER(_Request), C.POINTER(C.c_int64)], C.c_int32),
+        "nm_server_wait": ([P, C.c_int64, C.POINTER(C.POINTER(_ServerResult))], C.c_int32),
+        "nm_server_result_free": ([C.POINTER(_ServerResult)], None),
+        "nm_server_destroy": ([P], C.c_int32),
+        "nm_filtered_eig_slices": ([P, C.c_int32, P, P, P, C.c_double, C.POINTER(_EigOpts),
+                                    C.POINTER(C.POINTER(_EigResult))], C.c_int32),
         "nm_project_rotation": ([P, C.POINTER(_EigResult), C.c_double, C.c_double, P,
                                  C.POINTER(C.POINTER(_RotResult))], C.c_int32),
         "nm_result_copy_vectors": ([C.POINTER(_EigResult), P, C.c_int32], C.c_int32),
@@ -187,7 +210,7 @@ class EigResult:
 
 
 class RotResult:
-    def __init__(self, ptr):
+    def __init__(self, ptr, owned=True):
         r = ptr.contents
         self.count = r.count
         self.omega = np.array([r.omega[i] for i in range(r.count)])
@@ -197,7 +220,32 @@ class RotResult:
             buf = torch.empty((r.n, r.count, 2), dtype=torch.float64, device="cuda")
             _check(_lib.nm_rot_copy_vectors(ptr, _ptr(buf), 1))
             self.U = torch.view_as_complex(buf)
-        _lib.nm_rot_result_free(ptr)
+        if owned:
+            _lib.nm_rot_result_free(ptr)
+
+
+def _planet_structs(planet: dict, omega=None):
+    """nm_mesh / nm_material views of a planet dict (arrays kept alive in `keep`)."""
+    xyz = np.ascontiguousarray(planet["xyz"], np.float64)
+    tet = np.ascontiguousarray(planet["tet"], np.int32)
+    reg = np.ascontiguousarray(planet["region"], np.int8)
+    order, porder = int(planet["disp_order"]), int(planet["pres_order"])
+    rho = np.ascontiguousarray(planet["rho"], np.float64)
+    lam = np.ascontiguousarray(planet["lam"], np.float64)
+    mu = np.ascontiguousarray(planet["mu"], np.float64)
+    gp, dgp = planet.get("gprime"), planet.get("grad_gprime")
+    mesh = _Mesh(len(xyz), len(tet), _ptr(xyz), _ptr(tet), _ptr(reg), order, porder)
+    keep = [xyz, tet, reg, rho, lam, mu]
+    if gp is not None:
+        gp = np.ascontiguousarray(gp, np.float64)
+        dgp = np.ascontiguousarray(dgp, np.float64)
+        keep += [gp, dgp]
+        mat = _Material(_ptr(rho), _ptr(lam), _ptr(mu), _ptr(gp), _ptr(dgp), gp.shape[1])
+    else:
+        mat = _Material(_ptr(rho), _ptr(lam), _ptr(mu), None, None, 0)
+    om = np.ascontiguousarray(planet.get("omega", (0, 0, 0)) if omega is None else omega, np.float64)
+    keep.append(om)
+    return mesh, mat, om, keep
 
 
 class Pencil:
@@ -205,24 +253,7 @@ class Pencil:
 
     def __init__(self, planet: dict, omega=None):
         lib = load_library()
-        xyz = np.ascontiguousarray(planet["xyz"], np.float64)
-        tet = np.ascontiguousarray(planet["tet"], np.int32)
-        reg = np.ascontiguousarray(planet["region"], np.int8)
-        order, porder = int(planet["disp_order"]), int(planet["pres_order"])
-        rho = np.ascontiguousarray(planet["rho"], np.float64)
-        lam = np.ascontiguousarray(planet["lam"], np.float64)
-        mu = np.ascontiguousarray(planet["mu"], np.float64)
-        gp, dgp = planet.get("gprime"), planet.get("grad_gprime")
-        mesh = _Mesh(len(xyz), len(tet), _ptr(xyz), _ptr(tet), _ptr(reg), order, porder)
-        keep = [xyz, tet, reg, rho, lam, mu]
-        if gp is not None:
-            gp = np.ascontiguousarray(gp, np.float64)
-            dgp = np.ascontiguousarray(dgp, np.float64)
-            keep += [gp, dgp]
-            mat = _Material(_ptr(rho), _ptr(lam), _ptr(mu), _ptr(gp), _ptr(dgp), gp.shape[1])
-        else:
-            mat = _Material(_ptr(rho), _ptr(lam), _ptr(mu), None, None, 0)
-        om = np.ascontiguousarray(planet.get("omega", (0, 0, 0)) if omega is None else omega, np.float64)
+        mesh, mat, om, keep = _planet_structs(planet, omega)
         h = C.c_void_p()
         _check(lib.nm_assemble(C.byref(mesh), C.byref(mat), _ptr(om), _stream(), C.byref(h)))
         self._h = h
@@ -299,7 +330,89 @@ class Pencil:
         res.partial = False
         return res
 
+    def autotune(self, precision=0):
+        """Pick the fastest block width and mass-solve kernel; returns (block, microseconds per column-step)."""
+        blk, us = C.c_int32(), C.c_double()
+        _check(_lib.nm_pencil_autotune(self._h, int(precision), _stream(), C.byref(blk), C.byref(us)))
+        return blk.value, us.value
+
+    def filtered_eig_slices(self, windows, nev, tol, degree=0, block=0, precision=0, max_basis=0, null_filter=-1,
+                            verbose=0, minv_tol=0.0, kp_tol=0.0, lmin=0.0, lmax=0.0, guard=0.0, seed=1,
+                            allow_partial=False, refine=0):
+        """One solve per window (a, b), their filter applications batched; returns a list of EigResult."""
+        S = len(windows)
+        a = np.ascontiguousarray([w[0] for w in windows], np.float64)
+        b = np.ascontiguousarray([w[1] for w in windows], np.float64)
+        nv = np.ascontiguousarray(nev if np.ndim(nev) else [nev] * S, np.int32)
+        o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, lmin, lmax,
+                     guard, seed, _stream(), refine)
+        outs = (C.POINTER(_EigResult) * S)()
+        st = _lib.nm_filtered_eig_slices(self._h, S, _ptr(a), _ptr(b), _ptr(nv), tol, C.byref(o), outs)
+        if not (st == NM_PARTIAL and allow_partial):
+            _check(st)
+        res = []
+        for i in range(S):
+            r = EigResult(outs[i])
+            r.partial = st == NM_PARTIAL
+            res.append(r)
+        return res
+
     def project_rotation(self, basis: EigResult, a, b):
         r = C.POINTER(_RotResult)()
         _check(_lib.nm_project_rotation(self._h, basis._ptr, a, b, _stream(), C.byref(r)))
         return RotResult(r)
+
+
+class Server:
+    """Continuous batching of eigensolves on this GPU (see nm_server_create)."""
+
+    def __init__(self, hbm_budget_gb=200.0, max_active=4):
+        lib = load_library()
+        h = C.c_void_p()
+        _check(lib.nm_server_create(float(hbm_budget_gb) * 1e9, int(max_active), C.byref(h)))
+        self._h = h
+
+    def submit(self, planet: dict, windows, nev, tol, rotate=False, degree=0, block=0, precision=0, max_basis=0,
+               null_filter=-1, minv_tol=0.0, kp_tol=0.0, guard=0.0, seed=1, refine=0):
+        mesh, mat, om, keep = _planet_structs(planet)
+        S = len(windows)
+        a = np.ascontiguousarray([w[0] for w in windows], np.float64)
+        b = np.ascontiguousarray([w[1] for w in windows], np.float64)
+        nv = np.ascontiguousarray(nev if np.ndim(nev) else [nev] * S, np.int32)
+        o = _EigOpts(degree, block, precision, max_basis, null_filter, 0, minv_tol, kp_tol, 0.0, 0.0, guard, seed,
+                     None, refine)
+        req = _Request(mesh, mat, (C.c_double * 3)(*om), S, _ptr(a).value, _ptr(b).value, _ptr(nv).value, tol, o,
+                       1 if rotate else 0)
+        t = C.c_int64()
+        _check(_lib.nm_server_submit(self._h, C.byref(req), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket):
+        """Block until the request is done: dict(status, error, slices [EigResult], rotation, t_submit,
+        t_start, t_end, est_bytes)."""
+        r = C.POINTER(_ServerResult)()
+        _check(_lib.nm_server_wait(self._h, int(ticket), C.byref(r)))
+        c = r.contents
+        out = dict(status=c.status, error=c.error.decode(), t_submit=c.t_submit, t_start=c.t_start,
+                   t_end=c.t_end, est_bytes=c.est_bytes, slices=[], rotation=None)
+        for i in range(c.nslices):
+            if c.slices[i]:
+                e = EigResult(c.slices[i])
+                e.partial = c.status == NM_PARTIAL
+                e._ptr = None  # owned by the server result, freed below
+                out["slices"].append(e)
+        if c.rotation:
+            out["rotation"] = RotResult(c.rotation, owned=False)
+        _lib.nm_server_result_free(r)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _check(_lib.nm_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

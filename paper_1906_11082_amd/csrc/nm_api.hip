@@ -11,21 +11,7 @@ static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 }  // namespace nm
 
-#define NM_TRY(...)                                    \
-  try {                                                \
-    nm::set_error("");                                 \
-    __VA_ARGS__;                                       \
-    return NM_OK;                                      \
-  } catch (const nm::Error& e) {                       \
-    nm::set_error(e.what());                           \
-    return e.code;                                     \
-  } catch (const std::bad_alloc&) {                    \
-    nm::set_error("host allocation failed");           \
-    return NM_ENOMEM;                                  \
-  } catch (const std::exception& e) {                  \
-    nm::set_error(e.what());                           \
-    return NM_EDEVICE;                                 \
-  }
+
 
 namespace {
 template <class T>
@@ -211,6 +197,17 @@ nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const v
   })
 }
 
+nm_status nm_pencil_autotune(nm_pencil* p, int32_t precision, void* stream, int32_t* block, double* us_per_column) {
+  NM_TRY({
+    NM_REQUIRE(p && (precision == 0 || precision == 1), NM_EINVAL, "invalid arguments");
+    int b = 0;
+    double us = 0;
+    nm::autotune(p, precision, (hipStream_t)stream, &b, &us);
+    if (block) *block = b;
+    if (us_per_column) *us_per_column = us;
+  })
+}
+
 nm_status nm_filter_coeffs(double a, double b, double lmin, double lmax, int32_t m, double* mu) {
   NM_TRY({
     NM_REQUIRE(mu && m >= 0 && lmax > lmin && b > a, NM_EINVAL, "invalid filter arguments");
@@ -275,6 +272,22 @@ nm_status nm_filtered_eig(const nm_pencil* p, double a, double b, int32_t nev, d
       o.null_filter = -1;
     }
     nm::filtered_eig(p, a, b, nev, tol, o, out);
+  })
+}
+
+nm_status nm_filtered_eig_slices(const nm_pencil* p, int32_t nslices, const double* a, const double* b,
+                                 const int32_t* nev, double tol, const nm_eig_opts* opts, nm_eig_result** out) {
+  NM_TRY({
+    NM_REQUIRE(p && a && b && nev && out && nslices >= 1 && nslices <= 64, NM_EINVAL, "invalid arguments");
+    for (int i = 0; i < nslices; ++i) out[i] = nullptr;
+    nm_eig_opts o;
+    if (opts) o = *opts;
+    else {
+      std::memset(&o, 0, sizeof(o));
+      o.null_filter = -1;
+    }
+    std::vector<int> nv(nev, nev + nslices);
+    nm::filtered_eig_slices(p, nslices, a, b, nv.data(), tol, o, out);
   })
 }
 

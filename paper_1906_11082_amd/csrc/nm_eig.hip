@@ -214,6 +214,13 @@ void upper_inverse(int b, const std::vector<double>& R, std::vector<double>& Ri)
   }
 }
 
+// device -> host copy ordered on stream st (a plain hipMemcpy runs on the null
+// stream, which would serialise concurrent solves on their own streams)
+void d2h_sync(double* h, const double* d, size_t count, hipStream_t st) {
+  NM_HIP(hipMemcpyAsync(h, d, 8 * count, hipMemcpyDeviceToHost, st));
+  NM_HIP(hipStreamSynchronize(st));
+}
+
 struct Timer {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double s() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -249,7 +256,7 @@ void spectrum_bounds(const nm_pencil* P, int steps_req, uint64_t seed, hipStream
     apply_op(P, NM_OP_M, 1, v, mz.p, bc, st);
     double d;
     col_dots(n, 1, v, 1, mz.p, 1, dots.p, st);
-    NM_HIP(hipMemcpy(&d, dots.p, 8, hipMemcpyDeviceToHost));
+    d2h_sync(&d, dots.p, 1, st);
     return std::sqrt(std::max(d, 0.0));
   };
   double inv = 1.0 / mnorm(Vl.p);
@@ -291,7 +298,7 @@ void spectrum_bounds(const nm_pencil* P, int steps_req, uint64_t seed, hipStream
 }
 
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
-                  nm_eig_result** out) {
+                  nm_eig_result** out, FilterBatcher* fb, rocblas_handle blas) {
   NM_REQUIRE(b > a && nev > 0 && tol > 0, NM_EINVAL, "need a < b, nev > 0, tol > 0");
   hipStream_t st = (hipStream_t)o.stream;
   Timer clock;
@@ -299,7 +306,9 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   const int prec = o.precision;
   NM_REQUIRE(prec == 0 || prec == 1, NM_EINVAL, "precision must be 0 or 1");
   if (prec == 1) const_cast<nm_pencil*>(P)->ensure_fp32(st);
-  int bs = o.block > 0 ? o.block : 16;
+  // block width: given, else the autotuner's (at most nev / 4, in multiples of 8), else 16
+  int bs = o.block > 0 ? o.block
+                       : (P->tuned_block > 0 ? std::min(P->tuned_block, std::max(8, nev / 4 / 8 * 8)) : 16);
   bs = (int)std::min<int64_t>(bs, n);
   int Kmax = o.max_basis > 0 ? o.max_basis
                             : (int)std::min<int64_t>(n, std::max({6 * nev, nev + 16 * bs, 320}));
@@ -316,7 +325,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   cfg.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, mtol);
   cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, ptol);
   cfg.precision = prec;
-  Blas bl{P->blas};
+  Blas bl{blas ? blas : P->blas};
   NM_BLAS(rocblas_set_stream(bl.h, st));
   NM_BLAS(rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host));
 
@@ -336,6 +345,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   int mode = o.null_filter == 1 ? 2 : (o.null_filter == 0 ? 1 : (P->n_pres > 0 ? 0 : 1));
   if (o.null_filter == 2) mode = 0;
   const bool null = mode == 2;
+  NM_REQUIRE(!(null && fb), NM_EINVAL, "batched solves do not take the null factor");
   const double l0 = 0.0, s0 = null ? b : 0.0;
   const int m = o.degree > 0 ? o.degree : choose_degree(a, b, lmin, lmax, o.guard, mode);
   std::vector<double> mu(m + 1);
@@ -463,12 +473,65 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   int Kc_last = 0;
   std::vector<double> Ysel;  // col-major Kc x nsel
 
+  // Small problems are launch-bound (the filter is m (kM + ...) launches per
+  // block): capture one filter application into a HIP graph on a private
+  // stream, with fixed input and output buffers, and replay it for every
+  // block.  NM_GRAPH=0/1 overrides the size rule.
+  const char* genv = getenv("NM_GRAPH");
+  const bool use_graph = !fb && (genv ? atoi(genv) != 0 : (double)n * bs <= 4.0e6);
+  struct GraphState {
+    hipStream_t gs = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphState() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (gs) (void)hipStreamDestroy(gs);
+    }
+  } graph;
+  DBuf<double> gin, gout;
+  if (use_graph) {
+    NM_HIP(hipStreamCreateWithFlags(&graph.gs, hipStreamNonBlocking));
+    gin.alloc((size_t)n * bs);
+    gout.alloc((size_t)n * bs);
+  }
+
   for (int j = 0;; ++j) {
     const int Kj = K - bs;  // first column of the block to filter
     // ---- filter
     Timer ft;
     const double* vj = nullptr;
-    if (prec == 0) {
+    int napp = m + (null ? 1 : 0);
+    if (use_graph) {
+      NM_HIP(hipMemcpy2DAsync(gin.p, 8 * (size_t)bs, V.p + Kj, 8 * (size_t)Kmax, 8 * (size_t)bs, n,
+                              hipMemcpyDeviceToDevice, st));
+      NM_HIP(hipStreamSynchronize(st));
+      if (!graph.exec) {
+        ApplyCfg gc = cfg;
+        gc.prof = nullptr;  // no event records inside the graph
+        if (prec == 0) fw.ensure(P, bs);
+        else fw32.ensure(P, bs);
+        hipGraph_t g = nullptr;
+        NM_HIP(hipStreamBeginCapture(graph.gs, hipStreamCaptureModeThreadLocal));
+        if (prec == 0) {
+          filter_apply<double>(P, mu.data(), m, c, e, l0, s0, bs, gin.p, gout.p, gc, fw, graph.gs);
+        } else {
+          convert_f64_f32(n * bs, gin.p, x32.p, graph.gs);
+          filter_apply<float>(P, mu.data(), m, c, e, l0, s0, bs, x32.p, y32.p, gc, fw32, graph.gs);
+          convert_f32_f64(n * bs, y32.p, gout.p, graph.gs);
+        }
+        NM_HIP(hipStreamEndCapture(graph.gs, &g));
+        const hipError_t ie = hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        NM_HIP(ie);
+      }
+      NM_HIP(hipGraphLaunch(graph.exec, graph.gs));
+      NM_HIP(hipStreamSynchronize(graph.gs));
+      NM_HIP(hipMemcpyAsync(W.p, gout.p, 8 * (size_t)n * bs, hipMemcpyDeviceToDevice, st));
+    } else if (fb) {
+      NM_HIP(hipMemcpy2DAsync(T2.p, 8 * (size_t)bs, V.p + Kj, 8 * (size_t)Kmax, 8 * (size_t)bs, n,
+                              hipMemcpyDeviceToDevice, st));
+      NM_HIP(hipStreamSynchronize(st));
+      napp = fb->filter(T2.p, W.p, mu.data(), m, bs);
+    } else if (prec == 0) {
       fw.ensure(P, bs);
       NM_HIP(hipMemcpy2DAsync(fw.x0.p, 8 * (size_t)bs, V.p + Kj, 8 * (size_t)Kmax, 8 * (size_t)bs, n,
                               hipMemcpyDeviceToDevice, st));
@@ -484,7 +547,6 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     }
     NM_HIP(hipStreamSynchronize(st));
     filter_time += ft.s();
-    const int napp = m + (null ? 1 : 0);
     bapps += (int64_t)napp * bs;
     {
       // algorithmic bytes of one column B-application (matrices amortised over bs columns)
@@ -498,7 +560,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       std::vector<double> nr(bs);
       mprod(W.p, MW.p, bs);
       col_dots(n, bs, W.p, bs, MW.p, bs, Gd.p, st);
-      NM_HIP(hipMemcpy(nr.data(), Gd.p, 8 * bs, hipMemcpyDeviceToHost));
+      d2h_sync(nr.data(), Gd.p, bs, st);
       for (double x : nr)
         if (!std::isfinite(x) || x > 1e30)
           throw Error(NM_ENOCONV, "filter blow-up: the spectrum bound lambda_max is too small");
@@ -612,8 +674,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       col_dots(n, ns, AX.p, ns, AX.p, ns, rn.p, st);
       col_dots(n, ns, MX.p, ns, MX.p, ns, mn.p, st);
       std::vector<double> r2(ns), m2(ns);
-      NM_HIP(hipMemcpy(r2.data(), rn.p, 8 * ns, hipMemcpyDeviceToHost));
-      NM_HIP(hipMemcpy(m2.data(), mn.p, 8 * ns, hipMemcpyDeviceToHost));
+      d2h_sync(r2.data(), rn.p, ns, st);
+      d2h_sync(m2.data(), mn.p, ns, st);
       for (int i = 0; i < ns; ++i) {
         res_sel[i] = std::sqrt(r2[i]) / (std::fabs(th_sel[i]) * std::sqrt(m2[i]));
         if (!(res_sel[i] <= tol)) res_ok = false;
@@ -641,7 +703,16 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   }
 
   // ---------------- FP64 refinement of the window pairs
-  DBuf<double> Xref;  // refined Ritz vectors (internal order), [n][th_sel.size()]
+  // The refined set is the window Ritz vectors plus the Ritz vectors of the
+  // full basis just above the window, (b, b (1 + guard)], and below it (not
+  // the null cluster): the window vectors' remaining error lies mostly along
+  // those (the filter damps them least, the low-pass q below amplifies the
+  // ones under the window), so the Rayleigh-Ritz of the refined set needs
+  // them.  Every vector of the set is refined; the noisy basis itself is not
+  // used (it holds a second, noisy copy of each window eigenvector, and
+  // Rayleigh-Ritz over both mixes them).
+  DBuf<double> Xref;  // refined Ritz vectors (internal order), [n][xref_ld], window vectors first
+  int xref_ld = 0;
   int refine_passes = 0, kq = 0;
   int64_t refine_bapps = 0;
   Timer rclock;
@@ -650,152 +721,190 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     const int npass = o.refine > 0 ? o.refine : 3;
     const int ns0 = (int)th_sel.size();
     const int Kf = Kc_last;
+    const double gd = o.guard > 0 ? o.guard : 1.0;
+    // window vectors (restricted Rayleigh-Ritz) and band vectors (full Rayleigh-Ritz over V_f)
+    std::vector<double> Yband;
+    int nband = 0;
+    {
+      DBuf<double> HAf((size_t)Kf * Kf);
+      bl.tn(n, Kf, Kf, V.p, Kmax, AV.p, Kmax, HAf.p);
+      std::vector<double> h((size_t)Kf * Kf), thf, Zf;
+      NM_HIP(hipMemcpyAsync(h.data(), HAf.p, 8 * h.size(), hipMemcpyDeviceToHost, st));
+      NM_HIP(hipStreamSynchronize(st));
+      for (int q = 0; q < Kf; ++q)
+        for (int i = 0; i < q; ++i) h[i + (size_t)q * Kf] = h[q + (size_t)i * Kf] = 0.5 * (h[i + (size_t)q * Kf] + h[q + (size_t)i * Kf]);
+      sym_eig(Kf, h, thf, Zf);
+      for (int i = 0; i < Kf; ++i)
+        if ((thf[i] > b && thf[i] <= b * (1.0 + gd)) || (thf[i] < a && std::fabs(thf[i]) > 1e-6 * b)) {
+          Yband.insert(Yband.end(), Zf.begin() + (size_t)i * Kf, Zf.begin() + (size_t)(i + 1) * Kf);
+          ++nband;
+        }
+    }
+    int nsel = ns0;
+    const int qt0 = ns0 + nband;
+    DBuf<double> Xw((size_t)n * qt0);  // [window | band], row-major [n][qt]
+    {
+      std::vector<double> Ycat(Ysel.begin(), Ysel.begin() + (size_t)Kf * ns0);
+      Ycat.insert(Ycat.end(), Yband.begin(), Yband.end());
+      DBuf<double> Yd((size_t)Kf * qt0);
+      NM_HIP(hipMemcpyAsync(Yd.p, Ycat.data(), 8 * Ycat.size(), hipMemcpyHostToDevice, st));
+      bl.nn(n, Kf, qt0, 1.0, V.p, Kmax, Yd.p, Kf, 0.0, Xw.p, qt0);
+      NM_HIP(hipStreamSynchronize(st));
+    }
+    int qt = qt0;
+    // low-pass q(t) = T_k((c_q - t) / e_q) / T_k((c_q - b) / e_q) with [c_q -+ e_q] = [lc, lmax]:
+    // positive and decreasing below lc, 1 at b, |q| <= delta on [lc, lmax].  The rounding noise
+    // of the basis is spread over the spectrum and weighed by lambda_j / lambda in the residual;
+    // to lower the Lanczos floor r0 by f = tol / (10 r0), components above lc = lmax f^(2/3) are
+    // damped to delta = f / 3 (with a Weyl-law density the weighted noise below lc scales as
+    // (lc / lmax)^(3/2)).  q grows below b (by up to (6 / f)^0.41 at 0), so the refined vectors
+    // are Y = (B / b) q(B) X: the factor removes the exactly degenerate null space (the fluid
+    // kernel of the Cowling operator).
+    const double r0 = max_res();
+    const double f = std::min(0.5, std::max(1e-12, tol / (10.0 * r0)));
+    const double lc = std::min(std::max(b * (1.0 + gd), lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
+    const double tb = 1.0 + 2.0 * (lc - b) / (lmax - lc);
+    kq = std::max(2, (int)std::ceil(std::acosh(3.0 / f) / std::acosh(tb)));
+    std::vector<double> muq(kq + 1, 0.0);
+    muq[kq] = ((kq & 1) ? -1.0 : 1.0) / std::cosh(kq * std::acosh(tb));
+    const double cq = 0.5 * (lmax + lc), eq = 0.5 * (lmax - lc);
     ApplyCfg cfgq = cfg64;
     cfgq.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, std::min(1e-7, std::max(1e-12, 0.3 * tol)));
-    int nsel = ns0;
-    DBuf<double> Xw((size_t)n * nsel);
-    {
-      DBuf<double> Yd((size_t)Kf * nsel);
-      NM_HIP(hipMemcpyAsync(Yd.p, Ysel.data(), 8 * (size_t)Kf * nsel, hipMemcpyHostToDevice, st));
-      bl.nn(n, Kf, nsel, 1.0, V.p, Kmax, Yd.p, Kf, 0.0, Xw.p, nsel);
-    }
-    // H11 = V_f^T A V_f (fixed over the passes)
-    DBuf<double> H11((size_t)Kf * Kf);
-    bl.tn(n, Kf, Kf, V.p, Kmax, AV.p, Kmax, H11.p);
-    std::vector<double> h11((size_t)Kf * Kf);
-    NM_HIP(hipMemcpyAsync(h11.data(), H11.p, 8 * h11.size(), hipMemcpyDeviceToHost, st));
-    NM_HIP(hipStreamSynchronize(st));
-    H11.release();
     fw.ensure(P, bs);
+    double prev = r0;
     for (int pass = 0; pass < npass; ++pass) {
-      const int q = nsel;
-      // low-pass q(t) = T_k((c_q - t) / e_q) / T_k((c_q - b) / e_q) with [c_q -+ e_q] = [lc, lmax]:
-      // positive and decreasing below lc, 1 at b, |q| <= delta on [lc, lmax].  The rounding
-      // noise is spread over the spectrum and weighed by lambda_j / lambda in the residual; to
-      // lower the floor r0 by f = tol / (10 r0), components above lc = lmax f^(2/3) are damped
-      // to delta = f / 3 (with a Weyl-law density the weighted noise below lc scales as
-      // (lc / lmax)^(3/2))
-      const double r0 = max_res();
-      const double f = std::min(0.5, std::max(1e-12, tol / (10.0 * r0)));
-      const double lc = std::min(std::max(2.0 * b, lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
-      const double tb = 1.0 + 2.0 * (lc - b) / (lmax - lc);
-      kq = std::max(2, (int)std::ceil(std::acosh(3.0 / f) / std::acosh(tb)));
-      std::vector<double> muq(kq + 1, 0.0);
-      muq[kq] = ((kq & 1) ? -1.0 : 1.0) / std::cosh(kq * std::acosh(tb));
-      const double cq = 0.5 * (lmax + lc), eq = 0.5 * (lmax - lc);
-      // Y = q(B) X, bs columns at a time
+      const int q = qt;
+      // Y = (B / b) q(B) X, bs columns at a time
       DBuf<double> Yq((size_t)n * q), MY((size_t)n * q), AY((size_t)n * q);
       for (int j0 = 0; j0 < q; j0 += bs) {
         const int nc = std::min(bs, q - j0);
         NM_HIP(hipMemcpy2DAsync(T2.p, 8 * (size_t)nc, Xw.p + j0, 8 * (size_t)q, 8 * (size_t)nc, n,
                                 hipMemcpyDeviceToDevice, st));
-        filter_apply<double>(P, muq.data(), kq, cq, eq, 0.0, 0.0, nc, T2.p, W.p, cfgq, fw, st);
+        filter_apply<double>(P, muq.data(), kq, cq, eq, 0.0, b, nc, T2.p, W.p, cfgq, fw, st);
         NM_HIP(hipMemcpy2DAsync(Yq.p + j0, 8 * (size_t)q, W.p, 8 * (size_t)nc, 8 * (size_t)nc, n,
                                 hipMemcpyDeviceToDevice, st));
       }
-      refine_bapps += (int64_t)kq * q;
-      // M-orthogonalise against V_f (twice), then Cholesky QR (twice)
-      DBuf<double> Cq((size_t)Kf * q), Gq((size_t)q * q);
-      for (int it = 0; it < 2; ++it) {
+      refine_bapps += (int64_t)(kq + 1) * q;
+      // drop columns that the null factor has (numerically) annihilated, then
+      // M-orthonormalise by Cholesky QR (twice)
+      {
+        DBuf<double> nd(q);
         mprod(Yq.p, MY.p, q);
-        bl.tn(n, Kf, q, V.p, Kmax, MY.p, q, Cq.p);
-        bl.nn(n, Kf, q, -1.0, V.p, Kmax, Cq.p, Kf, 1.0, Yq.p, q);
+        col_dots(n, q, Yq.p, q, MY.p, q, nd.p, st);
+        std::vector<double> nrm(q);
+        d2h_sync(nrm.data(), nd.p, q, st);
+        const double mx = *std::max_element(nrm.begin(), nrm.end());
+        std::vector<int> live;
+        for (int k = 0; k < q; ++k)
+          if (nrm[k] > 1e-20 * mx) live.push_back(k);
+        if ((int)live.size() < q) {
+          const int ql = (int)live.size();
+          for (int k = 0; k < ql; ++k)
+            NM_HIP(hipMemcpy2DAsync(MY.p + k, 8 * (size_t)ql, Yq.p + live[k], 8 * (size_t)q, 8, n,
+                                    hipMemcpyDeviceToDevice, st));
+          NM_HIP(hipMemcpyAsync(Yq.p, MY.p, 8 * (size_t)n * ql, hipMemcpyDeviceToDevice, st));
+          qt = ql;
+        }
       }
+      const int q2 = qt;
+      DBuf<double> Gq((size_t)q2 * q2);
       bool ok = true;
       for (int it = 0; it < 2 && ok; ++it) {
-        mprod(Yq.p, MY.p, q);
-        bl.tn(n, q, q, Yq.p, q, MY.p, q, Gq.p);
-        std::vector<double> G((size_t)q * q), Ri;
+        mprod(Yq.p, MY.p, q2);
+        bl.tn(n, q2, q2, Yq.p, q2, MY.p, q2, Gq.p);
+        std::vector<double> G((size_t)q2 * q2), Ri;
         NM_HIP(hipMemcpyAsync(G.data(), Gq.p, 8 * G.size(), hipMemcpyDeviceToHost, st));
         NM_HIP(hipStreamSynchronize(st));
-        for (int i = 0; i < q; ++i)
-          for (int k = 0; k < i; ++k) G[i + (size_t)k * q] = G[k + (size_t)i * q] = 0.5 * (G[i + (size_t)k * q] + G[k + (size_t)i * q]);
-        chol_upper(q, G, ok);
+        for (int i = 0; i < q2; ++i)
+          for (int k = 0; k < i; ++k) G[i + (size_t)k * q2] = G[k + (size_t)i * q2] = 0.5 * (G[i + (size_t)k * q2] + G[k + (size_t)i * q2]);
+        chol_upper(q2, G, ok);
         if (!ok) break;
-        upper_inverse(q, G, Ri);
+        upper_inverse(q2, G, Ri);
         NM_HIP(hipMemcpyAsync(Gq.p, Ri.data(), 8 * Ri.size(), hipMemcpyHostToDevice, st));
-        bl.nn(n, q, q, 1.0, Yq.p, q, Gq.p, q, 0.0, MY.p, q);
+        bl.nn(n, q2, q2, 1.0, Yq.p, q2, Gq.p, q2, 0.0, MY.p, q2);
         std::swap(Yq.p, MY.p);
       }
-      if (!ok) break;  // the refined vectors are (numerically) in the basis already
-      apply_op(P, NM_OP_A, q, Yq.p, AY.p, cfg64, st);
-      // Rayleigh-Ritz with (A, M) on [V_f, Y]
-      const int Kt = Kf + q;
-      DBuf<double> H12((size_t)Kf * q), H22((size_t)q * q);
-      bl.tn(n, Kf, q, V.p, Kmax, AY.p, q, H12.p);
-      bl.tn(n, q, q, Yq.p, q, AY.p, q, H22.p);
-      std::vector<double> h12((size_t)Kf * q), h22((size_t)q * q), Ht((size_t)Kt * Kt);
-      NM_HIP(hipMemcpyAsync(h12.data(), H12.p, 8 * h12.size(), hipMemcpyDeviceToHost, st));
-      NM_HIP(hipMemcpyAsync(h22.data(), H22.p, 8 * h22.size(), hipMemcpyDeviceToHost, st));
+      if (!ok) break;  // the refined set is (numerically) rank deficient
+      apply_op(P, NM_OP_A, q2, Yq.p, AY.p, cfg64, st);
+      // Rayleigh-Ritz with (A, M) on span(Y)
+      DBuf<double> Hd((size_t)q2 * q2);
+      bl.tn(n, q2, q2, Yq.p, q2, AY.p, q2, Hd.p);
+      std::vector<double> Ht((size_t)q2 * q2), tht, Zt;
+      NM_HIP(hipMemcpyAsync(Ht.data(), Hd.p, 8 * Ht.size(), hipMemcpyDeviceToHost, st));
       NM_HIP(hipStreamSynchronize(st));
-      for (int jj = 0; jj < Kf; ++jj)
-        for (int i = 0; i < Kf; ++i)
-          Ht[i + (size_t)jj * Kt] = 0.5 * (h11[i + (size_t)jj * Kf] + h11[jj + (size_t)i * Kf]);
-      for (int jj = 0; jj < q; ++jj)
-        for (int i = 0; i < Kf; ++i)
-          Ht[i + (size_t)(Kf + jj) * Kt] = Ht[(Kf + jj) + (size_t)i * Kt] = h12[i + (size_t)jj * Kf];
-      for (int jj = 0; jj < q; ++jj)
-        for (int i = 0; i < q; ++i)
-          Ht[(Kf + i) + (size_t)(Kf + jj) * Kt] = 0.5 * (h22[i + (size_t)jj * q] + h22[jj + (size_t)i * q]);
-      std::vector<double> tht, Zt;
-      sym_eig(Kt, Ht, tht, Zt);
-      std::vector<int> cand;
-      for (int i = 0; i < Kt; ++i)
+      for (int i = 0; i < q2; ++i)
+        for (int k = 0; k < i; ++k) Ht[i + (size_t)k * q2] = Ht[k + (size_t)i * q2] = 0.5 * (Ht[i + (size_t)k * q2] + Ht[k + (size_t)i * q2]);
+      sym_eig(q2, Ht, tht, Zt);
+      std::vector<int> cand, keep;
+      for (int i = 0; i < q2; ++i) {
         if (tht[i] >= a && tht[i] <= b) cand.push_back(i);
+        if ((tht[i] > b && tht[i] <= b * (1.0 + gd)) || (tht[i] < a && std::fabs(tht[i]) > 1e-6 * b))
+          keep.push_back(i);
+      }
       const int nc = (int)cand.size();
       if (nc == 0) break;
-      std::vector<double> zv((size_t)Kf * nc), zy((size_t)q * nc), thc(nc);
-      for (int k = 0; k < nc; ++k) {
-        const double* zc = Zt.data() + (size_t)cand[k] * Kt;
-        std::copy(zc, zc + Kf, zv.begin() + (size_t)k * Kf);
-        std::copy(zc + Kf, zc + Kt, zy.begin() + (size_t)k * q);
-        thc[k] = tht[cand[k]];
-      }
-      DBuf<double> zvd((size_t)Kf * nc), zyd((size_t)q * nc), Xc((size_t)n * nc), AXc((size_t)n * nc),
-          MXc((size_t)n * nc), thd(nc), rn(nc), mn(nc);
-      NM_HIP(hipMemcpyAsync(zvd.p, zv.data(), 8 * zv.size(), hipMemcpyHostToDevice, st));
-      NM_HIP(hipMemcpyAsync(zyd.p, zy.data(), 8 * zy.size(), hipMemcpyHostToDevice, st));
+      // all window candidates and the band vectors of this Rayleigh-Ritz (next pass's set)
+      std::vector<int> all(cand);
+      all.insert(all.end(), keep.begin(), keep.end());
+      const int na = (int)all.size();
+      std::vector<double> za((size_t)q2 * na), thc(nc);
+      for (int k = 0; k < na; ++k)
+        std::copy(Zt.begin() + (size_t)all[k] * q2, Zt.begin() + (size_t)(all[k] + 1) * q2, za.begin() + (size_t)k * q2);
+      for (int k = 0; k < nc; ++k) thc[k] = tht[cand[k]];
+      DBuf<double> zad((size_t)q2 * na), Xc((size_t)n * na), AXc((size_t)n * nc), MXc((size_t)n * nc), thd(nc),
+          rn(nc), mn(nc);
+      NM_HIP(hipMemcpyAsync(zad.p, za.data(), 8 * za.size(), hipMemcpyHostToDevice, st));
       NM_HIP(hipMemcpyAsync(thd.p, thc.data(), 8 * nc, hipMemcpyHostToDevice, st));
-      bl.nn(n, Kf, nc, 1.0, V.p, Kmax, zvd.p, Kf, 0.0, Xc.p, nc);
-      bl.nn(n, q, nc, 1.0, Yq.p, q, zyd.p, q, 1.0, Xc.p, nc);
-      bl.nn(n, Kf, nc, 1.0, AV.p, Kmax, zvd.p, Kf, 0.0, AXc.p, nc);
-      bl.nn(n, q, nc, 1.0, AY.p, q, zyd.p, q, 1.0, AXc.p, nc);
-      mprod(Xc.p, MXc.p, nc);
+      bl.nn(n, q2, na, 1.0, Yq.p, q2, zad.p, q2, 0.0, Xc.p, na);
+      bl.nn(n, q2, nc, 1.0, AY.p, q2, zad.p, q2, 0.0, AXc.p, nc);
+      DBuf<double> Xwin((size_t)n * nc);
+      NM_HIP(hipMemcpy2DAsync(Xwin.p, 8 * (size_t)nc, Xc.p, 8 * (size_t)na, 8 * (size_t)nc, n,
+                              hipMemcpyDeviceToDevice, st));
+      mprod(Xwin.p, MXc.p, nc);
       hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n * nc)), dim3(256), 0, st, n, nc, AXc.p, MXc.p, thd.p,
                          AXc.p);
       col_dots(n, nc, AXc.p, nc, AXc.p, nc, rn.p, st);
       col_dots(n, nc, MXc.p, nc, MXc.p, nc, mn.p, st);
       std::vector<double> r2(nc), m2(nc), rc(nc);
-      NM_HIP(hipMemcpy(r2.data(), rn.p, 8 * nc, hipMemcpyDeviceToHost));
-      NM_HIP(hipMemcpy(m2.data(), mn.p, 8 * nc, hipMemcpyDeviceToHost));
+      d2h_sync(r2.data(), rn.p, nc, st);
+      d2h_sync(m2.data(), mn.p, nc, st);
       for (int k = 0; k < nc; ++k) rc[k] = std::sqrt(r2[k]) / (std::fabs(thc[k]) * std::sqrt(m2[k]));
-      // keep the ns0 candidates of smallest residual (window combinations of unconverged
-      // directions have residuals orders of magnitude above the refined pairs), ascending
+      // keep the ns0 window candidates of smallest residual, ascending
       std::vector<int> ord(nc);
       std::iota(ord.begin(), ord.end(), 0);
       std::sort(ord.begin(), ord.end(), [&](int x, int y) { return rc[x] < rc[y]; });
       ord.resize(std::min(nc, ns0));
       std::sort(ord.begin(), ord.end());
       nsel = (int)ord.size();
-      DBuf<double> Xn((size_t)n * nsel);
       th_sel.assign(nsel, 0.0);
       res_sel.assign(nsel, 0.0);
       bool all_ok = true;
+      // next set: [selected window vectors | band vectors]
+      const int nb2 = (int)keep.size();
+      DBuf<double> Xn((size_t)n * (nsel + nb2));
       for (int k = 0; k < nsel; ++k) {
         th_sel[k] = thc[ord[k]];
         res_sel[k] = rc[ord[k]];
         all_ok = all_ok && res_sel[k] <= tol;
-        NM_HIP(hipMemcpy2DAsync(Xn.p + k, 8 * (size_t)nsel, Xc.p + ord[k], 8 * (size_t)nc, 8, n,
+        NM_HIP(hipMemcpy2DAsync(Xn.p + k, 8 * (size_t)(nsel + nb2), Xc.p + ord[k], 8 * (size_t)na, 8, n,
                                 hipMemcpyDeviceToDevice, st));
       }
+      if (nb2)
+        NM_HIP(hipMemcpy2DAsync(Xn.p + nsel, 8 * (size_t)(nsel + nb2), Xc.p + nc, 8 * (size_t)na, 8 * (size_t)nb2, n,
+                                hipMemcpyDeviceToDevice, st));
       Xw = std::move(Xn);
+      qt = nsel + nb2;
       ++refine_passes;
       if (o.verbose)
-        fprintf(stderr, "[nmodes] refine pass %d degree %d pairs %d resid-max %.2e t=%.2fs\n", pass, kq, nsel,
-                max_res(), clock.s());
-      if (all_ok || max_res() > 0.5 * r0) break;
+        fprintf(stderr, "[nmodes] refine pass %d degree %d pairs %d (+%d above) resid-max %.2e t=%.2fs\n", pass, kq,
+                nsel, nb2, max_res(), clock.s());
+      if (all_ok || max_res() > 0.5 * prev) break;
+      prev = max_res();
     }
-    if (refine_passes > 0) Xref = std::move(Xw);
+    if (refine_passes > 0) {
+      Xref = std::move(Xw);  // window vectors first
+      xref_ld = qt;
+    }
   }
   const double refine_seconds = refine_passes > 0 ? rclock.s() : 0.0;
 
@@ -820,7 +929,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     // Ritz vectors in the internal node order, then to the canonical order
     DBuf<double> Xi((size_t)n * cnt);
     if (refine_passes > 0) {
-      NM_HIP(hipMemcpy2DAsync(Xi.p, 8 * (size_t)cnt, Xref.p, 8 * (size_t)ns, 8 * (size_t)cnt, n,
+      NM_HIP(hipMemcpy2DAsync(Xi.p, 8 * (size_t)cnt, Xref.p, 8 * (size_t)xref_ld, 8 * (size_t)cnt, n,
                               hipMemcpyDeviceToDevice, st));
     } else {
       DBuf<double> Yd((size_t)Kc_last * cnt);

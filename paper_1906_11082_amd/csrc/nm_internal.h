@@ -8,6 +8,9 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <condition_variable>
+#include <exception>
+#include <mutex>
 #include <vector>
 
 #include "../../include/nmodes.h"
@@ -20,6 +23,24 @@ struct Error : std::runtime_error {
 };
 
 void set_error(const std::string& m);
+
+// body of a C entry point: status codes, no exception crosses the ABI
+#define NM_TRY(...)                                    \
+  try {                                                \
+    nm::set_error("");                                 \
+    __VA_ARGS__;                                       \
+    return NM_OK;                                      \
+  } catch (const nm::Error& e) {                       \
+    nm::set_error(e.what());                           \
+    return e.code;                                     \
+  } catch (const std::bad_alloc&) {                    \
+    nm::set_error("host allocation failed");           \
+    return NM_ENOMEM;                                  \
+  } catch (const std::exception& e) {                  \
+    nm::set_error(e.what());                           \
+    return NM_EDEVICE;                                 \
+  }
+
 
 #define NM_HIP(x)                                                                       \
   do {                                                                                  \
@@ -124,6 +145,7 @@ struct nm_pencil {
   nm::DBuf<int32_t> grp_ptr, grp_col;
   nm::DBuf<double> grp_coef;
   int grouped = 1;  // 0: per-row kernels only; 1: grouped from 32 columns on; 2: grouped at any width
+  int tuned_block = 0;  // block width chosen by the autotuner (0: none)
   rocblas_handle blas = nullptr;
   void ensure_fp32(hipStream_t st);
 };
@@ -156,6 +178,8 @@ struct ApplyCfg {
   KernelProf* prof = nullptr;
 };
 int cheb_steps(double lo, double hi, double tol);
+// fastest block width and mass-solve kernel for this pencil (sets tuned_block and grouped)
+void autotune(nm_pencil* P, int precision, hipStream_t st, int* best_b, double* best_us_per_col);
 // operators on vectors in the internal node order
 void apply_op(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg,
               hipStream_t st);
@@ -171,12 +195,17 @@ template <class T>
 struct FilterWork {
   int b = 0;
   DBuf<T> x0, w0, w1, f, ya, yb, pt, ps, pa, pb;
+  DBuf<T> mucols;  // per-column series coefficients of filter_apply_cols
   void ensure(const nm_pencil* P, int ncols);
 };
 template <class T>
 void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0,
                   double s0, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
                   hipStream_t st);
+// one Chebyshev series per column: mu_cols host [m+1][ncols] (row k: the k-th coefficient of every column)
+template <class T>
+void filter_apply_cols(const nm_pencil* P, const double* mu_cols, int m, double c, double e, int ncols, const T* X,
+                       T* Y, const ApplyCfg& cfg, FilterWork<T>& w, hipStream_t st);
 template <class T>
 void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
              hipStream_t st);
@@ -193,8 +222,56 @@ int choose_degree(double a, double b, double lmin, double lmax, double guard, in
 double cheb_eval(const double* mu, int m, double t);
 
 void spectrum_bounds(const nm_pencil* P, int steps, uint64_t seed, hipStream_t st, double* lmin, double* lmax);
+// Filter applications of several concurrent solves on one pencil, batched
+// into one block (columns concatenated, one Chebyshev series per column):
+// every solve thread submits its block and waits; the submission that
+// completes the batch (all active solves waiting) runs it on the batch
+// stream.  All solves share the filter interval [c - e, c + e] and the
+// inner-solve configuration.
+class FilterBatcher {
+ public:
+  FilterBatcher(const nm_pencil* P, int precision, const ApplyCfg& cfg, double c, double e, int active,
+                hipStream_t st);
+  // X, Y: device FP64 [n][bs], X complete when called; returns the degree applied (the batch's largest;
+  // the series of lower-degree solves is zero-padded, which leaves their result unchanged)
+  int filter(const double* X, double* Y, const double* mu, int m, int bs);
+  // a solve stops submitting (finished or failed)
+  void leave();
+  KernelProf prof;
+
+ private:
+  struct Req {
+    const double* X;
+    double* Y;
+    const double* mu;
+    int m, bs, deg;
+    bool done;
+    std::exception_ptr err;
+  };
+  void run_locked();
+  const nm_pencil* P_;
+  int prec_;
+  ApplyCfg cfg_;
+  double c_, e_;
+  int active_;
+  hipStream_t st_;
+  std::mutex mx_;
+  std::condition_variable cv_;
+  std::vector<Req*> pend_;
+  FilterWork<double> fw_;
+  FilterWork<float> fw32_;
+  DBuf<double> xb_, yb_;
+  DBuf<float> x32_, y32_;
+};
+
+// fb: batch the filter applications with other solves (null factor not allowed);
+// blas: rocBLAS handle to use (null: the pencil's)
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
-                  nm_eig_result** out);
+                  nm_eig_result** out, FilterBatcher* fb = nullptr, rocblas_handle blas = nullptr);
+// one solve per window [a[i], b[i]] (nev[i] pairs), each in its own host thread and stream,
+// their filter applications batched; out[i] receives each result (NM_PARTIAL if any is partial)
+void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const double* b, const int* nev, double tol,
+                         const nm_eig_opts& o, nm_eig_result** out);
 void project_rotation(const nm_pencil* P, const nm_eig_result* basis, double a, double b,
                       hipStream_t st, nm_rot_result** out);
 

@@ -336,6 +336,19 @@ __global__ __launch_bounds__(256) void k_cj_first(uint32_t rows, uint32_t w, con
   stv<T, V>(y + o, x);
 }
 
+// filter-series coefficients of the V entries starting at column j of a row
+// [3][b]: one value for all columns, or per column (slices batched in one
+// block, each with its own polynomial)
+template <class T, int V>
+__device__ __forceinline__ void series_coef(T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc,
+                                            uint32_t j, T (&m0)[V], T (&m1)[V]) {
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    m0[i] = muc ? (mu0c ? mu0c[j + i] : T(0)) : mu0;
+    m1[i] = muc ? muc[j + i] : mu;
+  }
+}
+
 // One Chebyshev-Jacobi step.  mode 0: out = y_{j+1}.  mode 1: filter update
 // with z = y_{j+1}:  wout = a1 (z - cs win) + a2 wprev;
 // ymode 1: Yacc = mu0 win + mu wout; ymode 2: Yacc += mu wout.
@@ -347,7 +360,8 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
                                                  const T* __restrict__ dinv, const T* __restrict__ f,
                                                  const T* __restrict__ ycur, const T* yprev, T alpha, T beta,
                                                  int prev_zero, int mode, T* out, const T* __restrict__ win,
-                                                 const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, T* wout,
+                                                 const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu,
+                                                 const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
                                                  T* Yacc) {
   __shared__ int32_t s_col[STAGE_CAP];
   __shared__ T s_val[STAGE_CAP];
@@ -389,15 +403,18 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
     for (int i = 0; i < V; ++i) wo.v[i] += a2 * wp.v[i];
   }
   stv<T, V>(wout + o, wo);
+  if (ymode == 0) return;
+  T m0[V], m1[V];
+  series_coef<T, V>(mu0, mu, mu0c, muc, e % (w / 3), m0, m1);
   if (ymode == 1) {
     Vx<T, V> yy;
 #pragma unroll
-    for (int i = 0; i < V; ++i) yy.v[i] = mu0 * wi.v[i] + mu * wo.v[i];
+    for (int i = 0; i < V; ++i) yy.v[i] = m0[i] * wi.v[i] + m1[i] * wo.v[i];
     stv<T, V>(Yacc + o, yy);
   } else if (ymode == 2) {
     Vx<T, V> yy = ldv<T, V>(Yacc + o);
 #pragma unroll
-    for (int i = 0; i < V; ++i) yy.v[i] += mu * wo.v[i];
+    for (int i = 0; i < V; ++i) yy.v[i] += m1[i] * wo.v[i];
     stv<T, V>(Yacc + o, yy);
   }
 }
@@ -446,7 +463,8 @@ __global__ __launch_bounds__(256) void k_cj_group(
     uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
     const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
     const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
-    T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc) {
+    T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
+    T* Yacc) {
   constexpr int GCAP = 640;
   __shared__ int32_t s_col[GCAP];
   __shared__ T s_cf[GCAP * R];
@@ -507,15 +525,18 @@ __global__ __launch_bounds__(256) void k_cj_group(
       for (int i = 0; i < V; ++i) wo.v[i] += a2 * wp.v[i];
     }
     stv<T, V>(wout + o, wo);
+    if (ymode == 0) continue;
+    T m0[V], m1[V];
+    series_coef<T, V>(mu0, mu, mu0c, muc, e % (w / 3), m0, m1);
     if (ymode == 1) {
       Vx<T, V> yy;
 #pragma unroll
-      for (int i = 0; i < V; ++i) yy.v[i] = mu0 * wi.v[i] + mu * wo.v[i];
+      for (int i = 0; i < V; ++i) yy.v[i] = m0[i] * wi.v[i] + m1[i] * wo.v[i];
       stv<T, V>(Yacc + o, yy);
     } else if (ymode == 2) {
       Vx<T, V> yy = ldv<T, V>(Yacc + o);
 #pragma unroll
-      for (int i = 0; i < V; ++i) yy.v[i] += mu * wo.v[i];
+      for (int i = 0; i < V; ++i) yy.v[i] += m1[i] * wo.v[i];
       stv<T, V>(Yacc + o, yy);
     }
   }
@@ -619,14 +640,14 @@ GroupPlan group_plan(const nm_pencil* P, int b) {
 template <class T>
 void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const T* f, const T* ycur, const T* yprev,
                      T alpha, T beta, int prev_zero, int mode, T* out, const T* win, const T* wprev, T a1, T cs, T a2,
-                     int ymode, T mu0, T mu, T* wout, T* Yacc, hipStream_t st) {
+                     int ymode, T mu0, T mu, const T* mu0c, const T* muc, T* wout, T* Yacc, hipStream_t st) {
   const int v = pick_v<T>(w);
   const int64_t lanes = (N + tp.R - 1) / tp.R * (w / v);
   const T* cf = (const T*)tp.gcoef;
 #define NM_GRP(VV, RR)                                                                                              \
   hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,     \
                      tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,  \
-                     cs, a2, ymode, mu0, mu, wout, Yacc)
+                     cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
   if (tp.R == 8) {
     if (v == 4) NM_GRP(4, 8); else if (v == 2) NM_GRP(2, 8); else NM_GRP(1, 8);
   } else {
@@ -639,15 +660,16 @@ template <class T>
 void launch_cj_step(int64_t rows, int w, const int32_t* rp, const int32_t* col, const T* val, const T* dinv,
                     const T* f, const T* ycur, const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out,
                     const T* win, const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc,
-                    hipStream_t st, const GroupPlan* tp = nullptr) {
+                    hipStream_t st, const GroupPlan* tp = nullptr, const T* mu0c = nullptr,
+                    const T* muc = nullptr) {
   if (tp && tp->on) {
     launch_cj_group<T>(*tp, rows, w, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1, cs,
-                       a2, ymode, mu0, mu, wout, Yacc, st);
+                       a2, ymode, mu0, mu, mu0c, muc, wout, Yacc, st);
     return;
   }
   int v = pick_v<T>(w);
   NM_LAUNCH_V(k_cj_step, T, v, rows * (w / v), st, (uint32_t)rows, (uint32_t)w, rp, col, val, dinv, f, ycur, yprev,
-              alpha, beta, prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, mu0, mu, wout, Yacc);
+              alpha, beta, prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc);
 }
 template <class T>
 void launch_apply_ag(int64_t N, int b, const int32_t* rp, const int32_t* col, const T* ag, const T* X,
@@ -734,6 +756,8 @@ struct Update {
   int ymode = 0;
   void* wout = nullptr;
   void* Y = nullptr;
+  const void* mu0c = nullptr;  // per-column series coefficients (device, or null: mu0 / mu)
+  const void* muc = nullptr;
 };
 
 // z = S_M(A X); either written to Z or consumed by the filter update u
@@ -765,7 +789,8 @@ void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, 
     } else {
       launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 1, nullptr, (const T*)u.win, (const T*)u.wprev, (T)u.a1,
-                        (T)u.cs, (T)u.a2, u.ymode, (T)u.mu0, (T)u.mu, (T*)u.wout, (T*)u.Y, st, &tp);
+                        (T)u.cs, (T)u.a2, u.ymode, (T)u.mu0, (T)u.mu, (T*)u.wout, (T*)u.Y, st, &tp,
+                        (const T*)u.mu0c, (const T*)u.muc);
     }
   }
 }
@@ -795,10 +820,12 @@ void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cf
   b_apply_impl<T>(P, ncols, X, Y, Update{}, cfg.kM, cfg.kP, w, st);
 }
 
-// Y = p(B) X, or ((B - l0)/s0) p(B) X when s0 != 0; p = sum_k mu_k T_k((t - c)/e)
+// Y = p(B) X, or ((B - l0)/s0) p(B) X when s0 != 0; p = sum_k mu_k T_k((t - c)/e).
+// MUd (device, [m+1][ncols]) replaces mu by one series per column when set.
 template <class T>
-void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0, double s0, int ncols,
-                  const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w, hipStream_t st) {
+static void filter_run(const nm_pencil* P, const double* mu, const T* MUd, int m, double c, double e, double l0,
+                       double s0, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
+                       hipStream_t st) {
   w.ensure(P, ncols);
   const int64_t n = P->N * 3 * ncols;
   if (m == 0 && s0 == 0.0) {
@@ -823,7 +850,14 @@ void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double 
   const T* wprev = nullptr;
   {
     Update u;
-    u.on = true; u.win = win; u.a1 = 1.0 / e; u.cs = c; u.a2 = 0.0; u.ymode = 1; u.mu0 = mu[0]; u.mu = mu[1];
+    u.on = true; u.win = win; u.a1 = 1.0 / e; u.cs = c; u.a2 = 0.0; u.ymode = 1;
+    if (MUd) {
+      u.mu0c = MUd;
+      u.muc = MUd + ncols;
+    } else {
+      u.mu0 = mu[0];
+      u.mu = mu[1];
+    }
     u.wout = bufs[nb]; u.Y = Y;
     b_apply_impl<T>(P, ncols, win, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
     wprev = win;
@@ -834,7 +868,11 @@ void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double 
     // output buffer: the one holding wprev if it is a work buffer, else the free one
     T* out = (wprev == bufs[0] || wprev == bufs[1]) ? (T*)wprev : bufs[nb];
     Update u;
-    u.on = true; u.win = win; u.wprev = wprev; u.a1 = 2.0 / e; u.cs = c; u.a2 = -1.0; u.ymode = 2; u.mu = mu[k];
+    u.on = true; u.win = win; u.wprev = wprev; u.a1 = 2.0 / e; u.cs = c; u.a2 = -1.0; u.ymode = 2;
+    if (MUd)
+      u.muc = MUd + (size_t)k * ncols;
+    else
+      u.mu = mu[k];
     u.wout = out; u.Y = Y;
     b_apply_impl<T>(P, ncols, win, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
     wprev = win;
@@ -843,8 +881,96 @@ void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double 
   }
 }
 
+template <class T>
+void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0, double s0, int ncols,
+                  const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w, hipStream_t st) {
+  filter_run<T>(P, mu, nullptr, m, c, e, l0, s0, ncols, X, Y, cfg, w, st);
+}
+
+template <class T>
+void filter_apply_cols(const nm_pencil* P, const double* mu_cols, int m, double c, double e, int ncols, const T* X,
+                       T* Y, const ApplyCfg& cfg, FilterWork<T>& w, hipStream_t st) {
+  NM_REQUIRE(m >= 1, NM_EINVAL, "per-column filters need degree >= 1");
+  std::vector<T> h((size_t)(m + 1) * ncols);
+  for (size_t i = 0; i < h.size(); ++i) h[i] = (T)mu_cols[i];
+  w.ensure(P, ncols);
+  if (w.mucols.n < h.size()) w.mucols.alloc(h.size());
+  NM_HIP(hipMemcpyAsync(w.mucols.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, st));
+  filter_run<T>(P, nullptr, w.mucols.p, m, c, e, 0.0, 0.0, ncols, X, Y, cfg, w, st);
+  // the host table must outlive the copy
+  NM_HIP(hipStreamSynchronize(st));
+}
+
+// Autotuning of the mass-solve step, the hot loop of every filter step: for
+// block widths b in {8, 16, 32, 64} and, in FP64, the per-row and row-group
+// kernels, time `reps` middle Chebyshev-Jacobi steps with HIP events and keep
+// the fastest per column.  Sets the pencil's row-group mode to the winner's.
+template <class T>
+static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_us) {
+  auto m = mats<T>(P);
+  const int64_t N = P->N;
+  const int bmax = 64, reps = 8;
+  DBuf<T> f((size_t)N * 3 * bmax), y0((size_t)N * 3 * bmax), y1((size_t)N * 3 * bmax);
+  NM_HIP(hipMemsetAsync(f.p, 0, f.bytes(), st));
+  NM_HIP(hipMemsetAsync(y0.p, 0, y0.bytes(), st));
+  NM_HIP(hipMemsetAsync(y1.p, 0, y1.bytes(), st));
+  hipEvent_t e0, e1;
+  NM_HIP(hipEventCreate(&e0));
+  NM_HIP(hipEventCreate(&e1));
+  const int saved = P->grouped;
+  double best = 1e300;
+  int bb = 16, bg = saved;
+  const int modes[2] = {0, 2};
+  for (int b : {8, 16, 32, 64}) {
+    for (int gm : modes) {
+      if (gm == 2 && (sizeof(T) != 8 || P->grp_rows <= 0)) continue;
+      P->grouped = gm;
+      const GroupPlan tp = group_plan<T>(P, b);
+      const int wd = 3 * b;
+      auto step = [&]() {
+        launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, f.p, y0.p, y1.p, T(0.5), T(0.1), 0, 0, y1.p,
+                          nullptr, nullptr, T(0), T(0), T(0), 0, T(0), T(0), nullptr, nullptr, st, &tp);
+      };
+      step();
+      step();
+      NM_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < reps; ++r) step();
+      NM_HIP(hipEventRecord(e1, st));
+      NM_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      NM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / reps / b;
+      if (us < best) {
+        best = us;
+        bb = b;
+        bg = gm;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->grouped = bg;
+  P->tuned_block = bb;
+  *best_b = bb;
+  *best_us = best;
+}
+
+void autotune(nm_pencil* P, int precision, hipStream_t st, int* best_b, double* best_us) {
+  if (precision) {
+    P->ensure_fp32(st);
+    autotune_t<float>(P, st, best_b, best_us);
+  } else {
+    autotune_t<double>(P, st, best_b, best_us);
+  }
+  NM_HIP(hipStreamSynchronize(st));
+}
+
 template struct FilterWork<double>;
 template struct FilterWork<float>;
+template void filter_apply_cols<double>(const nm_pencil*, const double*, int, double, double, int, const double*,
+                                        double*, const ApplyCfg&, FilterWork<double>&, hipStream_t);
+template void filter_apply_cols<float>(const nm_pencil*, const double*, int, double, double, int, const float*,
+                                       float*, const ApplyCfg&, FilterWork<float>&, hipStream_t);
 template void b_apply<double>(const nm_pencil*, int, const double*, double*, const ApplyCfg&, FilterWork<double>&,
                               hipStream_t);
 template void b_apply<float>(const nm_pencil*, int, const float*, float*, const ApplyCfg&, FilterWork<float>&,
@@ -895,8 +1021,10 @@ static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* 
       break;
     }
     case NM_OP_A: {
+      // only the pressure-sized buffers of the Schur part are used
       FilterWork<T> w;
-      w.ensure(P, b);
+      const size_t np = (size_t)std::max<int64_t>(NP, 1) * b;
+      w.pt.alloc(np); w.pa.alloc(np); w.pb.alloc(np);
       a_apply<T>(P, b, X, Y, nullptr, 0.0, cfg.kP, w, st);
       NM_HIP(hipStreamSynchronize(st));
       break;

@@ -165,3 +165,68 @@ def test_empty_window_returns_no_pairs():
     G = nm.Pencil(d)
     r = G.filtered_eig(0.01, 0.05, 5, 1e-8, degree=30, block=4, max_basis=40, allow_partial=True)
     assert r.count == 0
+
+
+def test_slices_batched_equal_alone():
+    """Spectrum slicing with shared filter applications: two windows solved
+    together (one Lanczos per window, their filter blocks concatenated with
+    one Chebyshev series per column) give bit-identical eigenvalues to each
+    window solved alone with the same bounds and start block."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    print("\n[case] slices layered P2/P1 n_half=4", flush=True)
+    G = nm.Pencil(d)
+    lo, hi = G.spectrum_bounds()
+    lmin, lmax = lo - 0.01, hi
+    wins = [(1.0, 6.0), (6.0, 12.0)]
+    rs = G.filtered_eig_slices(wins, 100, 1e-9, block=8, lmin=lmin, lmax=lmax, seed=7)
+    assert len(rs) == 2
+    for i, (a, b) in enumerate(wins):
+        seed_i = (7 + 0x9E3779B97F4A7C15 * (i + 1)) % (1 << 64)
+        r1 = G.filtered_eig(a, b, 100, 1e-9, block=8, lmin=lmin, lmax=lmax, seed=seed_i)
+        print("slice %d: %d pairs, batched degree %d, alone degree %d" % (i, r1.count, rs[i].stats["degree"],
+                                                                        r1.stats["degree"]), flush=True)
+        assert r1.count == rs[i].count > 0
+        assert np.array_equal(r1.lam, rs[i].lam)
+        assert np.array_equal(r1.resid, rs[i].resid)
+        assert rs[i].resid.max() <= 1e-9
+    # together the windows cover [1, 12] once
+    allw = np.concatenate([r.lam for r in rs])
+    ref = G.filtered_eig(1.0, 12.0, 200, 1e-9, block=8, lmin=lmin, lmax=lmax)
+    assert len(allw) == ref.count
+    assert np.abs(np.sort(allw) - ref.lam).max() <= 1e-9 * ref.lam.max()
+
+
+def test_autotune_picks_a_block_and_solves():
+    """The autotuner times the mass-solve step for block widths 8..64 and both
+    kernels; the solve then uses the chosen width and finds the same pairs."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    G = nm.Pencil(d)
+    ref = G.filtered_eig(1.0, 12.0, 200, 1e-9, block=8)
+    blk, us = G.autotune(0)
+    print("autotune: block %d, %.3f us per column-step" % (blk, us), flush=True)
+    assert blk in (8, 16, 32, 64) and us > 0
+    r = G.filtered_eig(1.0, 12.0, 200, 1e-9, verbose=1)
+    assert r.stats["block"] == min(blk, 48)  # capped at nev / 4 in multiples of 8
+    assert r.count == ref.count
+    assert np.abs(r.lam - ref.lam).max() <= 1e-9 * ref.lam.max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replayed_filter_equals_eager(monkeypatch, precision):
+    """Small problems capture one filter application in a HIP graph and replay
+    it for every Lanczos block, with the orthogonalisation and Rayleigh-Ritz
+    running eagerly between the replays: the solve is bit-identical to the
+    eager one."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("homogeneous_ball", n_half=4, order=1)
+    G = nm.Pencil(d)
+    out = {}
+    for g in ("0", "1"):
+        monkeypatch.setenv("NM_GRAPH", g)
+        out[g] = G.filtered_eig(0.5, 40.0, 30, 1e-9, degree=40, block=8, precision=precision)
+    assert out["1"].count == out["0"].count == 30
+    assert np.array_equal(out["1"].lam, out["0"].lam)
+    assert np.array_equal(out["1"].X.cpu().numpy(), out["0"].X.cpu().numpy())
+    assert out["1"].stats["basis"] >= 24  # several blocks, so several replays
