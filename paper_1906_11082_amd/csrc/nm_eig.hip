@@ -753,18 +753,23 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     }
     int qt = qt0;
     // low-pass q(t) = T_k((c_q - t) / e_q) / T_k((c_q - b) / e_q) with [c_q -+ e_q] = [lc, lmax]:
-    // positive and decreasing below lc, 1 at b, |q| <= delta on [lc, lmax].  The rounding noise
-    // of the basis is spread over the spectrum and weighed by lambda_j / lambda in the residual;
-    // to lower the Lanczos floor r0 by f = tol / (10 r0), components above lc = lmax f^(2/3) are
-    // damped to delta = f / 3 (with a Weyl-law density the weighted noise below lc scales as
-    // (lc / lmax)^(3/2)).  q grows below b (by up to (6 / f)^0.41 at 0), so the refined vectors
-    // are Y = (B / b) q(B) X: the factor removes the exactly degenerate null space (the fluid
-    // kernel of the Cowling operator).
+    // positive and decreasing below lc, 1 at b, |q| <= d on [lc, lmax].  The rounding noise of
+    // the basis is spread over the spectrum and weighed by lambda_j / lambda in the residual; to
+    // lower the Lanczos floor r0 by f = tol / (10 r0), components above lc = lmax f^(2/3) are
+    // damped to d = f / 3 (with a Weyl-law density the weighted noise left below lc scales as
+    // (lc / lmax)^(3/2)).  q grows below b, by up to (6 / f)^0.41 at 0: harmless for the
+    // FP64-level null-space content of an FP64 basis, not for an FP32 one, whose refined vectors
+    // are therefore (B / b) q(B) X -- the factor removes the exactly degenerate null space (the
+    // fluid kernel of the Cowling operator) but multiplies components above b by lambda / b, so
+    // then lc = b (1 + guard) and d = (f / 3) b / lmax.
+    const bool nullf = prec == 1;
     const double r0 = max_res();
     const double f = std::min(0.5, std::max(1e-12, tol / (10.0 * r0)));
-    const double lc = std::min(std::max(b * (1.0 + gd), lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
+    const double lc = nullf ? b * (1.0 + gd)
+                            : std::min(std::max(b * (1.0 + gd), lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
+    const double dq = nullf ? f / 3.0 * b / lmax : f / 3.0;
     const double tb = 1.0 + 2.0 * (lc - b) / (lmax - lc);
-    kq = std::max(2, (int)std::ceil(std::acosh(3.0 / f) / std::acosh(tb)));
+    kq = std::max(2, (int)std::ceil(std::acosh(1.0 / dq) / std::acosh(tb)));
     std::vector<double> muq(kq + 1, 0.0);
     muq[kq] = ((kq & 1) ? -1.0 : 1.0) / std::cosh(kq * std::acosh(tb));
     const double cq = 0.5 * (lmax + lc), eq = 0.5 * (lmax - lc);
@@ -774,17 +779,17 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     double prev = r0;
     for (int pass = 0; pass < npass; ++pass) {
       const int q = qt;
-      // Y = (B / b) q(B) X, bs columns at a time
+      // Y = q(B) X (FP32 basis: (B / b) q(B) X), bs columns at a time
       DBuf<double> Yq((size_t)n * q), MY((size_t)n * q), AY((size_t)n * q);
       for (int j0 = 0; j0 < q; j0 += bs) {
         const int nc = std::min(bs, q - j0);
         NM_HIP(hipMemcpy2DAsync(T2.p, 8 * (size_t)nc, Xw.p + j0, 8 * (size_t)q, 8 * (size_t)nc, n,
                                 hipMemcpyDeviceToDevice, st));
-        filter_apply<double>(P, muq.data(), kq, cq, eq, 0.0, b, nc, T2.p, W.p, cfgq, fw, st);
+        filter_apply<double>(P, muq.data(), kq, cq, eq, 0.0, nullf ? b : 0.0, nc, T2.p, W.p, cfgq, fw, st);
         NM_HIP(hipMemcpy2DAsync(Yq.p + j0, 8 * (size_t)q, W.p, 8 * (size_t)nc, 8 * (size_t)nc, n,
                                 hipMemcpyDeviceToDevice, st));
       }
-      refine_bapps += (int64_t)(kq + 1) * q;
+      refine_bapps += (int64_t)(kq + (nullf ? 1 : 0)) * q;
       // drop columns that the null factor has (numerically) annihilated, then
       // M-orthonormalise by Cholesky QR (twice)
       {
