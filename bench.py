@@ -89,7 +89,8 @@ def main():
     ap.add_argument("--cpu-n-half", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_cj_step_c2.json"))
+    ap.add_argument("--traffic-json", default="", help="PMC traffic summary of the hot kernel (default: "
+                    "profiles/<kernel>_c2_<precision>_b<block>_traffic.json)")
     ap.add_argument("--quiet", action="store_true", help="no per-block progress lines on stderr")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -130,6 +131,10 @@ def main():
     st = last.stats
     hot_gbs = st["hot_bytes"] / (st["hot_ms"] * 1e-3) / 1e9 if st["hot_ms"] > 0 else None
     traffic = None
+    hot = "k_cj_group" if (prec == 0 and st["block"] >= 32) else "k_cj_step"
+    if not args.traffic_json:
+        args.traffic_json = os.path.join(ROOT, "profiles", "%s_c2_%s_b%d_traffic.json" % (hot, args.precision,
+                                                                                           st["block"]))
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
@@ -167,8 +172,7 @@ def main():
             "unit": "GB/s",
             "frac": hot_gbs / HBM_PEAK_GBS if hot_gbs else None,
             "traffic": traffic,
-            "kernel": ("k_cj_group" if (prec == 0 and st["block"] >= 32) else "k_cj_step")
-                      + " (fused Chebyshev-Jacobi step of the mass solve)",
+            "kernel": hot + " (fused Chebyshev-Jacobi step of the mass solve)",
             "bytes_per_launch": st["hot_bytes"],
             "mean_launch_ms": st["hot_ms"],
             "sampled_launches": st["hot_samples"],
