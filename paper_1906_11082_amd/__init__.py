@@ -373,14 +373,14 @@ class Server:
         self._h = h
 
     def submit(self, planet: dict, windows, nev, tol, rotate=False, degree=0, block=0, precision=0, max_basis=0,
-               null_filter=-1, minv_tol=0.0, kp_tol=0.0, guard=0.0, seed=1, refine=0):
+               null_filter=-1, minv_tol=0.0, kp_tol=0.0, guard=0.0, seed=1, refine=0, verbose=0):
         mesh, mat, om, keep = _planet_structs(planet)
         S = len(windows)
         a = np.ascontiguousarray([w[0] for w in windows], np.float64)
         b = np.ascontiguousarray([w[1] for w in windows], np.float64)
         nv = np.ascontiguousarray(nev if np.ndim(nev) else [nev] * S, np.int32)
-        o = _EigOpts(degree, block, precision, max_basis, null_filter, 0, minv_tol, kp_tol, 0.0, 0.0, guard, seed,
-                     None, refine)
+        o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, 0.0, 0.0, guard,
+                     seed, None, refine)
         req = _Request(mesh, mat, (C.c_double * 3)(*om), S, _ptr(a).value, _ptr(b).value, _ptr(nv).value, tol, o,
                        1 if rotate else 0)
         t = C.c_int64()

@@ -722,6 +722,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     const int ns0 = (int)th_sel.size();
     const int Kf = Kc_last;
     const double gd = o.guard > 0 ? o.guard : 1.0;
+    // FP32 basis: null factor in the refinement (see the low-pass below)
+    const bool nullf = prec == 1;
     // window vectors (restricted Rayleigh-Ritz) and band vectors (full Rayleigh-Ritz over V_f)
     std::vector<double> Yband;
     int nband = 0;
@@ -760,14 +762,13 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     // (lc / lmax)^(3/2)).  q grows below b, by up to (6 / f)^0.41 at 0: harmless for the
     // FP64-level null-space content of an FP64 basis, not for an FP32 one, whose refined vectors
     // are therefore (B / b) q(B) X -- the factor removes the exactly degenerate null space (the
-    // fluid kernel of the Cowling operator) but multiplies components above b by lambda / b, so
-    // then lc = b (1 + guard) and d = (f / 3) b / lmax.
-    const bool nullf = prec == 1;
+    // fluid kernel of the Cowling operator).  With the large degree an FP32 floor asks for, q
+    // falls fast enough above b to absorb the factor's growth lambda / b; with the small degree
+    // of an FP64 floor it would not, which is why FP64 goes without it.
     const double r0 = max_res();
     const double f = std::min(0.5, std::max(1e-12, tol / (10.0 * r0)));
-    const double lc = nullf ? b * (1.0 + gd)
-                            : std::min(std::max(b * (1.0 + gd), lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
-    const double dq = nullf ? f / 3.0 * b / lmax : f / 3.0;
+    const double lc = std::min(std::max(b * (1.0 + gd), lmax * std::pow(f, 2.0 / 3.0)), 0.5 * (b + lmax));
+    const double dq = f / 3.0;
     const double tb = 1.0 + 2.0 * (lc - b) / (lmax - lc);
     kq = std::max(2, (int)std::ceil(std::acosh(1.0 / dq) / std::acosh(tb)));
     std::vector<double> muq(kq + 1, 0.0);
@@ -811,24 +812,48 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
           qt = ql;
         }
       }
-      const int q2 = qt;
-      DBuf<double> Gq((size_t)q2 * q2);
+      // M-orthonormalise by an eigendecomposition of the scaled Gram matrix (twice), dropping
+      // directions below 1e-12 of the largest: the refined vectors can be nearly dependent
+      // (q is far from flat across the window when its degree is high)
       bool ok = true;
       for (int it = 0; it < 2 && ok; ++it) {
-        mprod(Yq.p, MY.p, q2);
-        bl.tn(n, q2, q2, Yq.p, q2, MY.p, q2, Gq.p);
-        std::vector<double> G((size_t)q2 * q2), Ri;
+        const int qc = qt;
+        DBuf<double> Gq((size_t)qc * qc);
+        mprod(Yq.p, MY.p, qc);
+        bl.tn(n, qc, qc, Yq.p, qc, MY.p, qc, Gq.p);
+        std::vector<double> G((size_t)qc * qc), gw, GU;
         NM_HIP(hipMemcpyAsync(G.data(), Gq.p, 8 * G.size(), hipMemcpyDeviceToHost, st));
         NM_HIP(hipStreamSynchronize(st));
-        for (int i = 0; i < q2; ++i)
-          for (int k = 0; k < i; ++k) G[i + (size_t)k * q2] = G[k + (size_t)i * q2] = 0.5 * (G[i + (size_t)k * q2] + G[k + (size_t)i * q2]);
-        chol_upper(q2, G, ok);
-        if (!ok) break;
-        upper_inverse(q2, G, Ri);
-        NM_HIP(hipMemcpyAsync(Gq.p, Ri.data(), 8 * Ri.size(), hipMemcpyHostToDevice, st));
-        bl.nn(n, q2, q2, 1.0, Yq.p, q2, Gq.p, q2, 0.0, MY.p, q2);
-        std::swap(Yq.p, MY.p);
+        std::vector<double> dsc(qc);
+        for (int i = 0; i < qc; ++i) dsc[i] = G[i + (size_t)i * qc] > 0 ? 1.0 / std::sqrt(G[i + (size_t)i * qc]) : 0.0;
+        for (int k = 0; k < qc; ++k)
+          for (int i = 0; i < qc; ++i) {
+            const double g = 0.5 * (G[i + (size_t)k * qc] + G[k + (size_t)i * qc]);
+            G[i + (size_t)k * qc] = dsc[i] * g * dsc[k];
+          }
+        sym_eig(qc, G, gw, GU);
+        const double wmax = gw.empty() ? 0.0 : gw.back();
+        std::vector<int> kept;
+        for (int k = 0; k < qc; ++k)
+          if (gw[k] > 1e-12 * wmax) kept.push_back(k);
+        const int r = (int)kept.size();
+        if (r == 0) {
+          ok = false;
+          break;
+        }
+        std::vector<double> Cm((size_t)qc * r);
+        for (int c2 = 0; c2 < r; ++c2) {
+          const int k = kept[c2];
+          const double sc = 1.0 / std::sqrt(gw[k]);
+          for (int i = 0; i < qc; ++i) Cm[i + (size_t)c2 * qc] = dsc[i] * GU[i + (size_t)k * qc] * sc;
+        }
+        DBuf<double> Cd2((size_t)qc * r);
+        NM_HIP(hipMemcpyAsync(Cd2.p, Cm.data(), 8 * Cm.size(), hipMemcpyHostToDevice, st));
+        bl.nn(n, qc, r, 1.0, Yq.p, qc, Cd2.p, qc, 0.0, MY.p, r);
+        NM_HIP(hipMemcpyAsync(Yq.p, MY.p, 8 * (size_t)n * r, hipMemcpyDeviceToDevice, st));
+        qt = r;
       }
+      const int q2 = qt;
       if (!ok) break;  // the refined set is (numerically) rank deficient
       apply_op(P, NM_OP_A, q2, Yq.p, AY.p, cfg64, st);
       // Rayleigh-Ritz with (A, M) on span(Y)

@@ -1,5 +1,6 @@
 """Serving workload: a seeded Poisson stream of eigensolve requests through
 the library's request server (continuous batching under an HBM budget).
+The solver's per-block log lines (stderr) show each request's progress.
 
 Per request (seeded): a layered planet with T tets drawn log-uniform in
 [tmin, tmax] (three-layer generator, n_half = (T / 48)^(1/3)), P1 or P2
@@ -72,7 +73,7 @@ def main():
             time.sleep(delay)
         sub = time.perf_counter() - t0
         tickets.append((r, sub, server.submit(planet, r["windows"], r["nev"], args.tol, rotate=r["omega"] > 0,
-                                              precision=prec, block=16)))
+                                              precision=prec, block=16, verbose=1)))
         print("[serve] submitted request %d (T=%d, P%d, %d windows) at %.2fs"
               % (len(tickets) - 1, len(planet["tet"]), r["order"], len(r["windows"]), sub), file=sys.stderr,
               flush=True)
