@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--traffic-json", default="", help="PMC traffic summary of the hot kernel (default: "
                     "profiles/<kernel>_c2_<precision>_b<block>_traffic.json)")
     ap.add_argument("--quiet", action="store_true", help="no per-block progress lines on stderr")
+    ap.add_argument("--omega", type=float, default=0.0,
+                    help="rotation rate about z: the step also projects the Coriolis term over the window's pairs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); --gpus %d is not supported"
@@ -104,14 +106,22 @@ def main():
 
     nm.load_library()
     torch.cuda.set_device(0)
-    planet = pg.three_layer_planet(n_half=args.n_half)
+    planet = pg.three_layer_planet(n_half=args.n_half, omega=(0.0, 0.0, args.omega))
     prec = 1 if args.precision == "fp32" else 0
+
+    rot = {}
 
     def step():
         P = nm.Pencil(planet)
         r = P.filtered_eig(args.a, args.b, args.nev, args.tol, block=args.block, guard=args.guard,
                            precision=prec, minv_tol=args.minv_tol, max_basis=args.max_basis,
                            verbose=0 if args.quiet else 1, allow_partial=True)
+        if args.omega != 0.0:
+            t = time.perf_counter()
+            rr = P.project_rotation(r, args.a, args.b)
+            rot.update(count=rr.count, seconds=time.perf_counter() - t,
+                       omega_min=float(rr.omega.min()) if rr.count else None,
+                       omega_max=float(rr.omega.max()) if rr.count else None)
         return P, r
 
     for _ in range(args.warmup):
@@ -164,6 +174,7 @@ def main():
             "partial": bool(last.partial),
             "refine_passes": st["refine_passes"], "refine_degree": st["refine_degree"],
             "refine_seconds": st["refine_seconds"], "refine_column_bapps": st["refine_bapps"],
+            "omega_z": args.omega, "rotating_modes": rot or None,
         },
         "roofline": {
             "bound": "hbm",

@@ -812,9 +812,10 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
           qt = ql;
         }
       }
-      // M-orthonormalise by an eigendecomposition of the scaled Gram matrix (twice), dropping
-      // directions below 1e-12 of the largest: the refined vectors can be nearly dependent
-      // (q is far from flat across the window when its degree is high)
+      // M-orthonormalise (twice): Cholesky QR, or, when the Gram matrix is numerically singular
+      // (the refined vectors can be nearly dependent: q is far from flat across the window when
+      // its degree is high), an eigendecomposition of the scaled Gram matrix that drops the
+      // directions below 1e-12 of the largest
       bool ok = true;
       for (int it = 0; it < 2 && ok; ++it) {
         const int qc = qt;
@@ -824,6 +825,21 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
         std::vector<double> G((size_t)qc * qc), gw, GU;
         NM_HIP(hipMemcpyAsync(G.data(), Gq.p, 8 * G.size(), hipMemcpyDeviceToHost, st));
         NM_HIP(hipStreamSynchronize(st));
+        {
+          std::vector<double> Gc(G), Ri;
+          for (int i = 0; i < qc; ++i)
+            for (int k = 0; k < i; ++k)
+              Gc[i + (size_t)k * qc] = Gc[k + (size_t)i * qc] = 0.5 * (Gc[i + (size_t)k * qc] + Gc[k + (size_t)i * qc]);
+          bool cok = true;
+          chol_upper(qc, Gc, cok);
+          if (cok) {
+            upper_inverse(qc, Gc, Ri);
+            NM_HIP(hipMemcpyAsync(Gq.p, Ri.data(), 8 * Ri.size(), hipMemcpyHostToDevice, st));
+            bl.nn(n, qc, qc, 1.0, Yq.p, qc, Gq.p, qc, 0.0, MY.p, qc);
+            std::swap(Yq.p, MY.p);
+            continue;
+          }
+        }
         std::vector<double> dsc(qc);
         for (int i = 0; i < qc; ++i) dsc[i] = G[i + (size_t)i * qc] > 0 ? 1.0 / std::sqrt(G[i + (size_t)i * qc]) : 0.0;
         for (int k = 0; k < qc; ++k)
