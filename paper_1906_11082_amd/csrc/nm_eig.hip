@@ -298,7 +298,8 @@ void spectrum_bounds(const nm_pencil* P, int steps_req, uint64_t seed, hipStream
 }
 
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
-                  nm_eig_result** out, FilterBatcher* fb, rocblas_handle blas) {
+                  nm_eig_result** out, BatchSeat* seat, rocblas_handle blas) {
+  FilterBatcher* fb = seat ? seat->fb : nullptr;
   NM_REQUIRE(b > a && nev > 0 && tol > 0, NM_EINVAL, "need a < b, nev > 0, tol > 0");
   hipStream_t st = (hipStream_t)o.stream;
   Timer clock;
@@ -701,6 +702,10 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     }
     if (K + bs > Kmax) break;
   }
+
+  // this solve submits no more filter blocks
+  if (seat) seat->leave();
+  fb = nullptr;
 
   // ---------------- FP64 refinement of the window pairs
   // The refined set is the window Ritz vectors plus the Ritz vectors of the

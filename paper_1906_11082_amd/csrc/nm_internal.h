@@ -264,10 +264,21 @@ class FilterBatcher {
   DBuf<float> x32_, y32_;
 };
 
-// fb: batch the filter applications with other solves (null factor not allowed);
+// One solve's place in a FilterBatcher: left once, when the solve stops filtering (the end
+// of its Lanczos loop, or an error), so the others' batches do not wait for its refinement.
+struct BatchSeat {
+  FilterBatcher* fb = nullptr;
+  bool left = false;
+  void leave() {
+    if (fb && !left) fb->leave();
+    left = true;
+  }
+};
+
+// seat: batch the filter applications with other solves (null factor not allowed);
 // blas: rocBLAS handle to use (null: the pencil's)
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
-                  nm_eig_result** out, FilterBatcher* fb = nullptr, rocblas_handle blas = nullptr);
+                  nm_eig_result** out, BatchSeat* seat = nullptr, rocblas_handle blas = nullptr);
 // one solve per window [a[i], b[i]] (nev[i] pairs), each in its own host thread and stream,
 // their filter applications batched; out[i] receives each result (NM_PARTIAL if any is partial)
 void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const double* b, const int* nev, double tol,

@@ -131,6 +131,7 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
     th.emplace_back([&, i]() {
       hipStream_t ss = nullptr;
       rocblas_handle h = nullptr;
+      BatchSeat seat{&fb};
       try {
         NM_HIP(hipSetDevice(dev));
         NM_HIP(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking));
@@ -140,7 +141,7 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
         oi.lmax = lmax;
         oi.stream = ss;
         oi.seed = o.seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
-        filtered_eig(P, a[i], b[i], nev[i], tol, oi, &out[i], &fb, h);
+        filtered_eig(P, a[i], b[i], nev[i], tol, oi, &out[i], &seat, h);
       } catch (const Error& e) {
         codes[i] = e.code;
         if (e.code != NM_PARTIAL) errs[i] = std::current_exception();
@@ -148,7 +149,7 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
         codes[i] = NM_EDEVICE;
         errs[i] = std::current_exception();
       }
-      fb.leave();
+      seat.leave();
       if (h) rocblas_destroy_handle(h);
       if (ss) (void)hipStreamDestroy(ss);
     });
