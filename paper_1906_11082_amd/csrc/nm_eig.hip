@@ -693,10 +693,14 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     // noise into every spectral component, which the residual weighs by
     // lambda_j / lambda: the window residuals stall at a floor.  Stop when
     // they are below tol or have stopped improving (refined below).
+    // With refinement available, residuals within 10 tol are handed to it as soon as p(B) has
+    // converged (the last block before the floor only shaves the residual there; at 100 tol the
+    // remaining error is partly unconverged Krylov directions, which the refinement cannot fix).
     const double res_max = ns ? *std::max_element(res_sel.begin(), res_sel.end()) : 0.0;
     const bool stalled = ns > 0 && prev_res_max > 0 && res_max > 0.5 * prev_res_max;
+    const bool refinable = o.refine >= 0 && ns > 0 && res_max <= 10.0 * tol;
     prev_res_max = res_max;
-    if ((res_ok || stalled) && stable && mu_ok) {
+    if ((res_ok || stalled || refinable) && stable && mu_ok) {
       converged = true;
       break;
     }

@@ -627,13 +627,15 @@ struct GroupPlan {
 template <class T>
 GroupPlan group_plan(const nm_pencil* P, int b) {
   GroupPlan tp;
-  if (sizeof(T) != 8 || !P->grouped || P->grp_rows <= 0 || b < 1) return tp;
-  if (P->grouped == 1 && b < 32) return tp;
+  if (!P->grouped || P->grp_rows <= 0 || b < 1) return tp;
+  if (P->grouped == 1 && (b < 32 || sizeof(T) != 8)) return tp;
+  const void* cf = sizeof(T) == 8 ? (const void*)P->grp_coef.p : (const void*)P->grp_coef32.p;
+  if (!cf) return tp;
   tp.on = true;
   tp.R = P->grp_rows;
   tp.gptr = P->grp_ptr.p;
   tp.gcol = P->grp_col.p;
-  tp.gcoef = P->grp_coef.p;
+  tp.gcoef = cf;
   return tp;
 }
 
@@ -1171,5 +1173,6 @@ void nm_pencil::ensure_fp32(hipStream_t st) {
   };
   cv(ag, ag32); cv(ms, ms32); cv(mdinv, mdinv32);
   cv(kp, kp32); cv(kpdinv, kpdinv32); cv(eg_val, eg_val32); cv(egt_val, egt_val32);
+  if (grp_rows > 0) cv(grp_coef, grp_coef32);
   NM_HIP(hipStreamSynchronize(st));
 }
