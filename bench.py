@@ -141,7 +141,7 @@ def main():
     st = last.stats
     hot_gbs = st["hot_bytes"] / (st["hot_ms"] * 1e-3) / 1e9 if st["hot_ms"] > 0 else None
     traffic = None
-    hot = "k_cj_group" if (prec == 0 and st["block"] >= 32) else "k_cj_step"
+    hot = "k_cj_group" if 3 * st["block"] * (4 if prec else 8) >= 768 else "k_cj_step"
     if not args.traffic_json:
         args.traffic_json = os.path.join(ROOT, "profiles", "%s_c2_%s_b%d_traffic.json" % (hot, args.precision,
                                                                                            st["block"]))

@@ -621,14 +621,16 @@ struct GroupPlan {
   const int32_t *gptr = nullptr, *gcol = nullptr;
   const void* gcoef = nullptr;
 };
-// FP64 only (in FP32 the per-row kernel measured as fast), and by default
-// only from 32 columns on: narrower blocks put more groups in a workgroup than
-// its LDS stage holds.  grouped == 2 forces the grouped kernel at any width.
+// By default only for rows of at least 768 bytes (FP64 from 32 columns, FP32
+// from 64): narrower rows put more groups in a workgroup than its LDS stage
+// holds, and measured slower than the per-row kernel (FP32, 32 columns: 0.45
+// vs 0.42 ms; 64 columns: 0.63 vs 0.78 ms).  grouped == 2 forces the grouped
+// kernel at any width.
 template <class T>
 GroupPlan group_plan(const nm_pencil* P, int b) {
   GroupPlan tp;
   if (!P->grouped || P->grp_rows <= 0 || b < 1) return tp;
-  if (P->grouped == 1 && (b < 32 || sizeof(T) != 8)) return tp;
+  if (P->grouped == 1 && 3 * (size_t)b * sizeof(T) < 768) return tp;
   const void* cf = sizeof(T) == 8 ? (const void*)P->grp_coef.p : (const void*)P->grp_coef32.p;
   if (!cf) return tp;
   tp.on = true;

@@ -183,8 +183,8 @@ def test_assembly_is_deterministic(torch_cuda):
 def test_row_group_kernel_matches_per_row(torch_cuda, ncols, monkeypatch):
     """The row-group mass-solve kernel (4 or 8 Morton rows per lane, union
     columns with zero-padded coefficients) sums each row in the same column
-    order as the per-row kernel: FP64 results are bit-identical, including
-    the ragged last group."""
+    order as the per-row kernel: FP64 and FP32 results are bit-identical,
+    including the ragged last group."""
     torch = torch_cuda
     import paper_1906_11082_amd as nm
     d = dict(make_planet("three_layer_planet", n_half=5, order=2, pres_order=1))
@@ -200,6 +200,9 @@ def test_row_group_kernel_matches_per_row(torch_cuda, ncols, monkeypatch):
     c, e = 2.0e3, 2.0e3
     ref_m = pens["row"].apply(nm.OP_MINV, X, kM=17)
     ref_f = pens["row"].filter_apply(mu, c, e, X, kM=6, kP=5)
+    X32 = X.float()
+    ref_32 = pens["row"].apply(nm.OP_MINV, X32, kM=17, precision=1)
     for tag in ("g4", "g8"):
         assert torch.equal(pens[tag].apply(nm.OP_MINV, X, kM=17), ref_m), tag
         assert torch.equal(pens[tag].filter_apply(mu, c, e, X, kM=6, kP=5), ref_f), tag
+        assert torch.equal(pens[tag].apply(nm.OP_MINV, X32, kM=17, precision=1), ref_32), tag
