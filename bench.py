@@ -96,7 +96,7 @@ def main():
                     help="rotation rate about z: the step also projects the Coriolis term over the window's pairs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); --gpus %d is not supported"
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
