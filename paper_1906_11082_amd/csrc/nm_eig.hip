@@ -679,7 +679,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       d2h_sync(m2.data(), mn.p, ns, st);
       for (int i = 0; i < ns; ++i) {
         res_sel[i] = std::sqrt(r2[i]) / (std::fabs(th_sel[i]) * std::sqrt(m2[i]));
-        if (!(res_sel[i] <= tol)) res_ok = false;
+        if (i < nev && !(res_sel[i] <= tol)) res_ok = false;  // the pairs returned: the nev lowest
       }
     }
     if (o.verbose)
@@ -696,7 +696,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     // With refinement available, residuals within 10 tol are handed to it as soon as p(B) has
     // converged (the last block before the floor only shaves the residual there; at 100 tol the
     // remaining error is partly unconverged Krylov directions, which the refinement cannot fix).
-    const double res_max = ns ? *std::max_element(res_sel.begin(), res_sel.end()) : 0.0;
+    const int nret = std::min(ns, nev);
+    const double res_max = nret ? *std::max_element(res_sel.begin(), res_sel.begin() + nret) : 0.0;
     const bool stalled = ns > 0 && prev_res_max > 0 && res_max > 0.5 * prev_res_max;
     const bool refinable = o.refine >= 0 && ns > 0 && res_max <= 10.0 * tol;
     prev_res_max = res_max;
@@ -725,7 +726,11 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   int refine_passes = 0, kq = 0;
   int64_t refine_bapps = 0;
   Timer rclock;
-  auto max_res = [&]() { return res_sel.empty() ? 0.0 : *std::max_element(res_sel.begin(), res_sel.end()); };
+  // largest residual among the pairs returned (the nev lowest of the window)
+  auto max_res = [&]() {
+    const size_t k = std::min(res_sel.size(), (size_t)nev);
+    return k ? *std::max_element(res_sel.begin(), res_sel.begin() + k) : 0.0;
+  };
   if (o.refine >= 0 && !th_sel.empty() && max_res() > tol) {
     const int npass = o.refine > 0 ? o.refine : 3;
     const int ns0 = (int)th_sel.size();
@@ -940,7 +945,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       for (int k = 0; k < nsel; ++k) {
         th_sel[k] = thc[ord[k]];
         res_sel[k] = rc[ord[k]];
-        all_ok = all_ok && res_sel[k] <= tol;
+        all_ok = all_ok && (k >= nev || res_sel[k] <= tol);
         NM_HIP(hipMemcpy2DAsync(Xn.p + k, 8 * (size_t)(nsel + nb2), Xc.p + ord[k], 8 * (size_t)na, 8, n,
                                 hipMemcpyDeviceToDevice, st));
       }

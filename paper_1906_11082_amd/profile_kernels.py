@@ -6,8 +6,8 @@
 
 Launches, on the three-layer planet at n_half (default 20): `reps` M-solves
 of `steps` Chebyshev-Jacobi steps on a block of `block` columns (so the
-middle-step kernel dominates: k_cj_group for FP64 blocks of 32 columns or
-more, k_cj_step otherwise), one filter application of degree `degree`, and a
+middle-step kernel dominates: k_cj_group for rows of 768 bytes or more --
+FP64 from 32 columns, FP32 from 64 -- and k_cj_step otherwise), one filter application of degree `degree`, and a
 plain device copy of `copy_mb` MB (torch) that calibrates the HBM byte
 counters.  Prints the algorithmic bytes of one middle-step launch so the
 counters can be compared with it.
