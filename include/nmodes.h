@@ -124,6 +124,10 @@ typedef struct {
   double minv_tol;     /* bound 2 r^k of the M solve (0 = 1e-12) */
   double kp_tol;       /* bound of the K_p solve (0 = 1e-13) */
   int32_t precision;   /* 0 FP64, 1 FP32 values, vectors and accumulation */
+  int32_t mass_passes; /* M solve of NM_OP_MINV / NM_OP_B and nm_filter_apply, precision 0:
+                          0 one FP64 Chebyshev-Jacobi pass; P = 2..8: P passes in FP32 with
+                          FP64 residual corrections (see nm_filtered_eig), each of kM steps
+                          if kM > 0, else of the steps that bring (2 r^k)^P to minv_tol */
 } nm_apply_opts;
 
 typedef struct {
@@ -143,6 +147,8 @@ typedef struct {
   void* stream;        /* hipStream_t */
   int32_t refine;      /* at most this many FP64 refinement passes of the window pairs
                           (0 = 3, -1 = none; see nm_filtered_eig) */
+  int32_t mass_passes; /* M solve inside an FP64 filter: 0 one FP64 pass; P = 2..8 passes in
+                          FP32 with FP64 residual corrections (see nm_filtered_eig) */
 } nm_eig_opts;
 
 typedef struct {
@@ -170,6 +176,8 @@ typedef struct {
   int32_t refine_passes, refine_degree;
   double refine_seconds;
   int64_t refine_bapps;
+  /* M solve inside the filter: FP32 passes (0: one FP64 pass of kM steps) and steps per pass */
+  int32_t mass_passes, mass_pass_steps;
 } nm_eig_result;
 
 typedef struct {
@@ -251,10 +259,18 @@ nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, v
  * vectors and accumulation: eps32) leaves the window residuals at a floor
  * near eps * lambda_max / lambda.  The Lanczos therefore stops when they are
  * below tol or no longer improve, and the window pairs are refined in FP64:
- * each pass applies (B / b) q(B), q a Chebyshev low-pass polynomial (1 at b,
- * small beyond a cut-off chosen from the floor), to the window Ritz vectors
- * and to those just above the window, and runs Rayleigh-Ritz on (A, M) over
- * the refined vectors.  NM_PARTIAL:
+ * each pass applies q(B) ((B / b) q(B) after an FP32 filter), q a Chebyshev
+ * low-pass polynomial (1 at b, small beyond a cut-off chosen from the floor),
+ * to the window Ritz vectors and to those just above and below the window,
+ * and runs Rayleigh-Ritz on (A, M) over the refined vectors.
+ * opts->mass_passes P >= 2 (precision 0): every M solve inside the filter
+ * runs as P Chebyshev-Jacobi passes in FP32, the first on A W, each later one
+ * on the FP64 residual of the sum so far, with the sum kept in FP64
+ * (iterative refinement of the solve; the paper fixes only that M^{-1} is
+ * applied through products with M, Sec. 6.1).  Its error operator (I - S M)^P
+ * has the bound of one FP64 pass of P k steps, and the rounding a pass leaves
+ * is relative to the correction it computes; the refinement above runs in
+ * FP64 throughout.  NM_PARTIAL:
  * the pairs returned are those found, some with residual above tol, or the
  * basis cap was reached first. */
 nm_status nm_filtered_eig(const nm_pencil* p, double a, double b, int32_t nev, double tol,

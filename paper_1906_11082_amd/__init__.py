@@ -57,14 +57,14 @@ class _Info(C.Structure):
 
 class _ApplyOpts(C.Structure):
     _fields_ = [("kM", C.c_int32), ("kP", C.c_int32), ("minv_tol", C.c_double), ("kp_tol", C.c_double),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("mass_passes", C.c_int32)]
 
 
 class _EigOpts(C.Structure):
     _fields_ = [("degree", C.c_int32), ("block", C.c_int32), ("precision", C.c_int32), ("max_basis", C.c_int32),
                 ("null_filter", C.c_int32), ("verbose", C.c_int32), ("minv_tol", C.c_double),
                 ("kp_tol", C.c_double), ("lmin", C.c_double), ("lmax", C.c_double), ("guard", C.c_double),
-                ("seed", C.c_uint64), ("stream", C.c_void_p), ("refine", C.c_int32)]
+                ("seed", C.c_uint64), ("stream", C.c_void_p), ("refine", C.c_int32), ("mass_passes", C.c_int32)]
 
 
 class _EigResult(C.Structure):
@@ -74,7 +74,8 @@ class _EigResult(C.Structure):
                 ("lmin", C.c_double), ("lmax", C.c_double), ("seconds", C.c_double), ("bytes", C.c_double),
                 ("filter_seconds", C.c_double), ("hot_launches", C.c_int64), ("hot_samples", C.c_int64),
                 ("hot_ms", C.c_double), ("hot_bytes", C.c_double), ("refine_passes", C.c_int32),
-                ("refine_degree", C.c_int32), ("refine_seconds", C.c_double), ("refine_bapps", C.c_int64)]
+                ("refine_degree", C.c_int32), ("refine_seconds", C.c_double), ("refine_bapps", C.c_int64),
+                ("mass_passes", C.c_int32), ("mass_pass_steps", C.c_int32)]
 
 
 class _RotResult(C.Structure):
@@ -195,7 +196,8 @@ class EigResult:
                           filter_seconds=r.filter_seconds, hot_launches=r.hot_launches,
                           hot_samples=r.hot_samples, hot_ms=r.hot_ms, hot_bytes=r.hot_bytes,
                           refine_passes=r.refine_passes, refine_degree=r.refine_degree,
-                          refine_seconds=r.refine_seconds, refine_bapps=r.refine_bapps)
+                          refine_seconds=r.refine_seconds, refine_bapps=r.refine_bapps,
+                          mass_passes=r.mass_passes, mass_pass_steps=r.mass_pass_steps)
         self._ptr = ptr
         self.n = r.n
         self.X = None
@@ -286,8 +288,8 @@ class Pencil:
         return ng, pg[:self.n_p]
 
     @staticmethod
-    def _opts(kM=0, kP=0, minv_tol=0.0, kp_tol=0.0, precision=0):
-        return _ApplyOpts(kM, kP, minv_tol, kp_tol, precision)
+    def _opts(kM=0, kP=0, minv_tol=0.0, kp_tol=0.0, precision=0, mass_passes=0):
+        return _ApplyOpts(kM, kP, minv_tol, kp_tol, precision, mass_passes)
 
     def apply(self, op, X, out_rows=None, **kw):
         """Y = op(X) for a device tensor X [rows, ncols] (float64, or float32
@@ -316,9 +318,9 @@ class Pencil:
 
     def filtered_eig(self, a, b, nev, tol, degree=0, block=0, precision=0, max_basis=0, null_filter=-1,
                      verbose=0, minv_tol=0.0, kp_tol=0.0, lmin=0.0, lmax=0.0, guard=0.0, seed=1,
-                     allow_partial=False, refine=0):
+                     allow_partial=False, refine=0, mass_passes=0):
         o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, lmin, lmax,
-                     guard, seed, _stream(), refine)
+                     guard, seed, _stream(), refine, mass_passes)
         r = C.POINTER(_EigResult)()
         st = _lib.nm_filtered_eig(self._h, a, b, nev, tol, C.byref(o), C.byref(r))
         if st == NM_PARTIAL and allow_partial and r:
@@ -338,14 +340,14 @@ class Pencil:
 
     def filtered_eig_slices(self, windows, nev, tol, degree=0, block=0, precision=0, max_basis=0, null_filter=-1,
                             verbose=0, minv_tol=0.0, kp_tol=0.0, lmin=0.0, lmax=0.0, guard=0.0, seed=1,
-                            allow_partial=False, refine=0):
+                            allow_partial=False, refine=0, mass_passes=0):
         """One solve per window (a, b), their filter applications batched; returns a list of EigResult."""
         S = len(windows)
         a = np.ascontiguousarray([w[0] for w in windows], np.float64)
         b = np.ascontiguousarray([w[1] for w in windows], np.float64)
         nv = np.ascontiguousarray(nev if np.ndim(nev) else [nev] * S, np.int32)
         o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, lmin, lmax,
-                     guard, seed, _stream(), refine)
+                     guard, seed, _stream(), refine, mass_passes)
         outs = (C.POINTER(_EigResult) * S)()
         st = _lib.nm_filtered_eig_slices(self._h, S, _ptr(a), _ptr(b), _ptr(nv), tol, C.byref(o), outs)
         if not (st == NM_PARTIAL and allow_partial):
@@ -373,14 +375,14 @@ class Server:
         self._h = h
 
     def submit(self, planet: dict, windows, nev, tol, rotate=False, degree=0, block=0, precision=0, max_basis=0,
-               null_filter=-1, minv_tol=0.0, kp_tol=0.0, guard=0.0, seed=1, refine=0, verbose=0):
+               null_filter=-1, minv_tol=0.0, kp_tol=0.0, guard=0.0, seed=1, refine=0, verbose=0, mass_passes=0):
         mesh, mat, om, keep = _planet_structs(planet)
         S = len(windows)
         a = np.ascontiguousarray([w[0] for w in windows], np.float64)
         b = np.ascontiguousarray([w[1] for w in windows], np.float64)
         nv = np.ascontiguousarray(nev if np.ndim(nev) else [nev] * S, np.int32)
         o = _EigOpts(degree, block, precision, max_basis, null_filter, verbose, minv_tol, kp_tol, 0.0, 0.0, guard,
-                     seed, None, refine)
+                     seed, None, refine, mass_passes)
         req = _Request(mesh, mat, (C.c_double * 3)(*om), S, _ptr(a).value, _ptr(b).value, _ptr(nv).value, tol, o,
                        1 if rotate else 0)
         t = C.c_int64()

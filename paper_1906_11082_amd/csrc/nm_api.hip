@@ -22,7 +22,7 @@ std::vector<T> d2h(const T* d, size_t n) {
 }
 }  // namespace
 
-static nm::ApplyCfg make_cfg(const nm_pencil* p, const nm_apply_opts* o) {
+static nm::ApplyCfg make_cfg(const nm_pencil* p, const nm_apply_opts* o, hipStream_t st) {
   nm::ApplyCfg c;
   double mt = (o && o->minv_tol > 0) ? o->minv_tol : 1e-12;
   double pt = (o && o->kp_tol > 0) ? o->kp_tol : 1e-13;
@@ -31,6 +31,7 @@ static nm::ApplyCfg make_cfg(const nm_pencil* p, const nm_apply_opts* o) {
   c.precision = o ? o->precision : 0;
   NM_REQUIRE(c.precision == 0 || c.precision == 1, NM_EINVAL, "precision must be 0 or 1");
   NM_REQUIRE(c.kM >= 2 && c.kP >= 1, NM_EINVAL, "kM must be >= 2 and kP >= 1");
+  nm::set_mass_passes(const_cast<nm_pencil*>(p), c, o ? o->mass_passes : 0, mt, (o && o->kM > 0) ? o->kM : 0, st);
   return c;
 }
 
@@ -193,7 +194,7 @@ nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const v
                           const nm_apply_opts* opts, void* stream) {
   NM_TRY({
     NM_REQUIRE(p && X && Y && X != Y, NM_EINVAL, "invalid pointers");
-    nm::api_apply(p, op, ncols, X, Y, make_cfg(p, opts), (hipStream_t)stream);
+    nm::api_apply(p, op, ncols, X, Y, make_cfg(p, opts, (hipStream_t)stream), (hipStream_t)stream);
   })
 }
 
@@ -229,8 +230,8 @@ nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, doubl
                           void* stream) {
   NM_TRY({
     NM_REQUIRE(p && mu && X && Y && X != Y && m >= 0 && e > 0 && ncols > 0, NM_EINVAL, "invalid filter arguments");
-    auto cfg = make_cfg(p, opts);
     hipStream_t st = (hipStream_t)stream;
+    auto cfg = make_cfg(p, opts, st);
     // vectors cross the ABI in canonical node order; the filter runs in the internal order
     const int eb = cfg.precision == 1 ? 4 : 8;
     const int64_t w = 3 * (int64_t)ncols;

@@ -326,6 +326,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   cfg.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, mtol);
   cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, ptol);
   cfg.precision = prec;
+  set_mass_passes(const_cast<nm_pencil*>(P), cfg, o.mass_passes, mtol, 0, st);
   Blas bl{blas ? blas : P->blas};
   NM_BLAS(rocblas_set_stream(bl.h, st));
   NM_BLAS(rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host));
@@ -508,8 +509,12 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       if (!graph.exec) {
         ApplyCfg gc = cfg;
         gc.prof = nullptr;  // no event records inside the graph
-        if (prec == 0) fw.ensure(P, bs);
-        else fw32.ensure(P, bs);
+        if (prec == 0) {
+          fw.ensure(P, bs);
+          if (cfg.mixP) fw.ensure_mixed(P, bs);
+        } else {
+          fw32.ensure(P, bs);
+        }
         hipGraph_t g = nullptr;
         NM_HIP(hipStreamBeginCapture(graph.gs, hipStreamCaptureModeThreadLocal));
         if (prec == 0) {
@@ -554,6 +559,17 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       const double s = prec ? 4.0 : 8.0;
       const double nnzb = (double)P->nnzb;
       double per = (nnzb * (9 * s + 4) + (cfg.kM - 1) * nnzb * (s + 4)) / bs + (4.0 * (cfg.kM - 1) + 4.0) * n * s;
+      if (cfg.mixP) {
+        // A (FP64 values, X, F), the first iterate (f, f32, y), FP32 steps (values and 4
+        // streams), residuals (FP64 values; y, r in, r32, next iterate, and where kept the
+        // FP64 residual and the sum) and the final sum with the filter update (5 streams)
+        const int Pm = cfg.mixP;
+        per = nnzb * (9 * 8.0 + 4) / bs + 16.0 * n + 16.0 * n + Pm * (cfg.mixK - 1.0) * (nnzb * 8.0 / bs + 16.0 * n);
+        for (int q = 0; q + 1 < Pm; ++q)
+          per += nnzb * 12.0 / bs + 20.0 * n + (q + 2 < Pm ? 8.0 * n : 0.0) +
+                 (q >= 1 ? 8.0 * n + (q >= 2 ? 8.0 * n : 4.0 * n) : 0.0);
+        per += (Pm >= 3 ? 12.0 : 8.0) * n + 40.0 * n;
+      }
       bytes += per * napp * bs;
     }
     // ---- blow-up guard
@@ -1016,9 +1032,12 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   r->hot_samples = prof.samples;
   r->hot_ms = prof.samples ? prof.ms / prof.samples : 0.0;
   {
-    const double sz = prec ? 4.0 : 8.0;
+    // a middle step of the FP64 mass solve, or of an FP32 pass of the mixed one
+    const double sz = (prec || cfg.mixP) ? 4.0 : 8.0;
     r->hot_bytes = (double)P->nnzb * (4.0 + sz) + 4.0 * (P->N + 1) + sz * P->N + 4.0 * n * bs * sz;
   }
+  r->mass_passes = cfg.mixP;
+  r->mass_pass_steps = cfg.mixP ? cfg.mixK : cfg.kM;
   r->refine_passes = refine_passes;
   r->refine_degree = kq;
   r->refine_seconds = refine_seconds;

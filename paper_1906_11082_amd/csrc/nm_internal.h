@@ -176,9 +176,15 @@ struct KernelProf {
 struct ApplyCfg {
   int kM = 0, kP = 0;
   int precision = 0;
+  // mass solve of an FP64 filter as mixP >= 2 FP32 Chebyshev-Jacobi passes of
+  // mixK steps with FP64 residual corrections between them (0: one FP64 pass of kM)
+  int mixP = 0, mixK = 0;
   KernelProf* prof = nullptr;
 };
 int cheb_steps(double lo, double hi, double tol);
+// sets cfg.mixP / mixK for `passes` (0 or 2..8; FP64 filters only) from the overall
+// bound mtol, or kM_pass steps per pass when > 0; creates the FP32 shadows it reads
+void set_mass_passes(nm_pencil* P, ApplyCfg& cfg, int passes, double mtol, int kM_pass, hipStream_t st);
 // fastest block width and mass-solve kernel for this pencil (sets tuned_block and grouped)
 void autotune(nm_pencil* P, int precision, hipStream_t st, int* best_b, double* best_us_per_col);
 // operators on vectors in the internal node order
@@ -197,7 +203,9 @@ struct FilterWork {
   int b = 0;
   DBuf<T> x0, w0, w1, f, ya, yb, pt, ps, pa, pb;
   DBuf<T> mucols;  // per-column series coefficients of filter_apply_cols
+  DBuf<float> s0, s1, s2, s3;  // FP32 right-hand side, iterates and first result of the mixed mass solve
   void ensure(const nm_pencil* P, int ncols);
+  void ensure_mixed(const nm_pencil* P, int ncols);
 };
 template <class T>
 void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0,

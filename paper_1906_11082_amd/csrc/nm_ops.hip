@@ -123,9 +123,10 @@ __device__ __forceinline__ Stage<T, NV> stage_rows(const int32_t* __restrict__ r
 // global arrays in separate calls, so that after inlining the compiler knows
 // each pointer's address space: LDS reads become ds_read (not flat loads,
 // which would occupy the texture-address unit that the gathers saturate).
-template <class T, int V, int U = 8>
+// X may hold a narrower type TX than the values and the sum (FP32 rows, FP64 values).
+template <class T, int V, int U = 8, class TX = T>
 __device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int32_t base, int32_t k0, int32_t k1,
-                                             const T* __restrict__ X, uint32_t w, uint32_t e) {
+                                             const TX* __restrict__ X, uint32_t w, uint32_t e) {
   Vx<T, V> acc;
 #pragma unroll
   for (int i = 0; i < V; ++i) acc.v[i] = T(0);
@@ -141,13 +142,13 @@ __device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int
       const T av = vl[kk];
       a[u] = in ? av : T(0);
     }
-    Vx<T, V> x[U];
+    Vx<TX, V> x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
+    for (int u = 0; u < U; ++u) x[u] = ldv<TX, V>(X + (size_t)(c[u] * w + e));
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int i = 0; i < V; ++i) acc.v[i] += a[u] * x[u].v[i];
+      for (int i = 0; i < V; ++i) acc.v[i] += a[u] * (T)x[u].v[i];
   }
   return acc;
 }
@@ -155,46 +156,51 @@ __device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int
 // flat index of this lane in a launch covering rows * (w / V) lanes
 __device__ __forceinline__ uint32_t lane_id() { return (uint32_t)nm_xcd_block() * blockDim.x + threadIdx.x; }
 
-// sum over the row's 3x3 blocks of (block row c) . X[col] (3 gathered V-vectors
-// per block); cl / vl as in row_spmv (LDS or global arrays, entry k at k - base)
-template <class T, int V>
-__device__ __forceinline__ Vx<T, V> ag_row(const int32_t* cl, const T* vl, int32_t base, int32_t k0, int32_t k1,
-                                           const T* __restrict__ X, uint32_t w, uint32_t b, uint32_t c,
-                                           uint32_t v) {
-  Vx<T, V> acc;
+// sum over the row's 3x3 blocks of block . X[col] for the three output
+// components: 3 gathered V-vectors per block (columns v..v+V of the three
+// components of the neighbour), shared by the three outputs; cl / vl as in
+// row_spmv (LDS or global arrays, entry k at k - base).  Per output the
+// products are added block by block, d = 0, 1, 2 within a block.
+template <class T, int V, int U = 2>
+__device__ __forceinline__ void ag_row(const int32_t* cl, const T* vl, int32_t base, int32_t k0, int32_t k1,
+                                       const T* __restrict__ X, uint32_t w, uint32_t b, uint32_t v,
+                                       Vx<T, V> (&acc)[3]) {
 #pragma unroll
-  for (int i = 0; i < V; ++i) acc.v[i] = T(0);
-  for (int32_t k = k0; k < k1; k += 4) {
-    uint32_t cc[4];
-    T a[4][3];
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool in = k + u < k1;
-      const int32_t kk = (in ? k + u : k0) - base;
-      cc[u] = (uint32_t)cl[kk];
+    for (int i = 0; i < V; ++i) acc[c].v[i] = T(0);
+  for (int32_t k = k0; k < k1; k += U) {
+    uint32_t cc[U];
+    bool in[U];
+    int32_t kk[U];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const T av = vl[9 * (size_t)kk + 3 * c + d];
-        a[u][d] = in ? av : T(0);
-      }
+    for (int u = 0; u < U; ++u) {
+      in[u] = k + u < k1;
+      kk[u] = (in[u] ? k + u : k0) - base;
+      cc[u] = (uint32_t)cl[kk[u]];
     }
-    Vx<T, V> x[4][3];
+    Vx<T, V> x[U][3];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int d = 0; d < 3; ++d) x[u][d] = ldv<T, V>(X + (size_t)(cc[u] * w + d * b + v));
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int i = 0; i < V; ++i) acc.v[i] += a[u][d] * x[u][d].v[i];
+        for (int d = 0; d < 3; ++d) {
+          const T av = vl[9 * (size_t)kk[u] + 3 * c + d];
+          const T a = in[u] ? av : T(0);
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc[c].v[i] += a * x[u][d].v[i];
+        }
   }
-  return acc;
 }
 
 // F = A_G X [+ E_G S] ; optionally Y1 = D^{-1} F / theta (first Chebyshev iterate).
-// Lane (row, c, column group of V): 3 block entries and 3 gathered V-vectors per nonzero block.
+// Lane (row, column group of V): all three components, so each neighbour
+// row is gathered once per row (b / V lanes, 3 gathered V-vectors each).
 template <class T, int V>
 __global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const T* __restrict__ ag,
@@ -205,12 +211,12 @@ __global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const 
   constexpr int CAP = STAGE_CAP / 4;
   __shared__ int32_t s_col[CAP];
   __shared__ T s_val[9 * CAP];
-  const uint32_t w = 3 * b, wl = w / V;
+  const uint32_t w = 3 * b, bl = b / V;
   const uint32_t g = lane_id();
-  const bool active = g < N * wl;
+  const bool active = g < N * bl;
   // stage (indices and 3x3 blocks) of this workgroup's rows
   const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
-  const uint32_t r0 = min(g0 / wl, N - 1), r1 = min((g0 + blockDim.x - 1) / wl, N - 1);
+  const uint32_t r0 = min(g0 / bl, N - 1), r1 = min((g0 + blockDim.x - 1) / bl, N - 1);
   const int32_t kb = rp[r0], ke = rp[r1 + 1];
   const bool staged = ke - kb <= CAP;
   if (staged) {
@@ -219,28 +225,36 @@ __global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const 
   }
   __syncthreads();
   if (!active) return;
-  const uint32_t row = g / wl;
-  const uint32_t e = (g - row * wl) * V;
-  const uint32_t c = e / b, v = e - c * b;
+  const uint32_t row = g / bl;
+  const uint32_t v = (g - row * bl) * V;
   const int32_t k0 = rp[row], k1 = rp[row + 1];
-  Vx<T, V> acc = staged ? ag_row<T, V>(s_col, s_val, kb, k0, k1, X, w, b, c, v)
-                        : ag_row<T, V>(col, ag, 0, k0, k1, X, w, b, c, v);
+  Vx<T, V> acc[3];
+  if (staged)
+    ag_row<T, V>(s_col, s_val, kb, k0, k1, X, w, b, v, acc);
+  else
+    ag_row<T, V>(col, ag, 0, k0, k1, X, w, b, v, acc);
   if (S) {
     for (int32_t q = egp[row]; q < egp[row + 1]; ++q) {
-      const T ev = egv[3 * (size_t)q + c];
-      Vx<T, V> s = ldv<T, V>(S + (size_t)((uint32_t)egc[q] * b + v));
+      const Vx<T, V> sv = ldv<T, V>(S + (size_t)((uint32_t)egc[q] * b + v));
 #pragma unroll
-      for (int i = 0; i < V; ++i) acc.v[i] += ev * s.v[i];
+      for (int c = 0; c < 3; ++c) {
+        const T ev = egv[3 * (size_t)q + c];
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[c].v[i] += ev * sv.v[i];
+      }
     }
   }
-  const size_t o = (size_t)row * w + e;
-  if (F) stv<T, V>(F + o, acc);
-  if (Y1) {
-    const T sc = dinv[row] * inv_theta;
-    Vx<T, V> y;
+  const T sc = Y1 ? dinv[row] * inv_theta : T(0);
 #pragma unroll
-    for (int i = 0; i < V; ++i) y.v[i] = sc * acc.v[i];
-    stv<T, V>(Y1 + o, y);
+  for (int c = 0; c < 3; ++c) {
+    const size_t o = (size_t)row * w + c * b + v;
+    if (F) stv<T, V>(F + o, acc[c]);
+    if (Y1) {
+      Vx<T, V> y;
+#pragma unroll
+      for (int i = 0; i < V; ++i) y.v[i] = sc * acc[c].v[i];
+      stv<T, V>(Y1 + o, y);
+    }
   }
 }
 
@@ -542,6 +556,144 @@ __global__ __launch_bounds__(256) void k_cj_group(
   }
 }
 
+// ---- mass solve in FP32 passes with FP64 residual corrections
+// (iterative refinement of the Chebyshev-Jacobi solve): pass 1 solves
+// M y_1 = f, pass p solves M y_p = r_{p-1} with r_p = r_{p-1} - M y_p formed
+// in FP64 from the FP32 result (which converts to FP64 exactly, so r_p carries
+// FP64 rounding only), and the solution y_1 + ... + y_P is summed in FP64.  With S the fixed-k solve,
+// the error operator is (I - S M)^P, so P passes of k steps reach the bound
+// (2 r^k)^P of one FP64 pass of P k steps, while rounding of each FP32 pass
+// is relative to the correction it computes.
+
+// pass 1, first iterate: f32 = f, y = D^{-1} f / theta (FP32)
+template <int V>
+__global__ __launch_bounds__(256) void k_mix_first(uint32_t rows, uint32_t w, const double* __restrict__ dinv,
+                                                   const double* __restrict__ f, double inv_theta,
+                                                   float* __restrict__ f32, float* __restrict__ y) {
+  const uint32_t wl = w / V;
+  const uint32_t g = lane_id();
+  if (g >= rows * wl) return;
+  const uint32_t row = g / wl, e = (g - row * wl) * V;
+  const size_t o = (size_t)row * w + e;
+  const Vx<double, V> x = ldv_nt<double, V>(f + o);
+  const double sc = dinv[row] * inv_theta;
+  Vx<float, V> a, b;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    a.v[i] = (float)x.v[i];
+    b.v[i] = (float)(sc * x.v[i]);
+  }
+  stv<float, V>(f32 + o, a);
+  stv<float, V>(y + o, b);
+}
+
+// the FP64 sum of the passes so far plus this pass's y: acc_in (FP64) and
+// y0 (the first pass's result, kept in FP32 until a second one is added)
+// may each be absent
+template <int V>
+__device__ __forceinline__ Vx<double, V> pass_sum(const double* acc_in, const float* __restrict__ y0,
+                                                  const Vx<float, V>& y, size_t o) {
+  Vx<double, V> a;
+  if (acc_in) {
+    a = ldv<double, V>(acc_in + o);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) a.v[i] = 0.0;
+  }
+  if (y0) {
+    const Vx<float, V> q = ldv<float, V>(y0 + o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) a.v[i] += (double)q.v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) a.v[i] += (double)y.v[i];
+  return a;
+}
+
+// between passes: r = rin - M y (FP64, y the FP32 result of the pass),
+// r32 = r, ynext = D^{-1} r / theta (first iterate of the next pass); rout
+// (if set) = r for a later residual, acc_out (if set) = the sum of the
+// passes so far (pass_sum).  rout may alias rin and acc_out acc_in (each lane
+// reads, then writes, its own entries); y is only read.
+template <int V>
+__global__ __launch_bounds__(256) void k_mix_resid(uint32_t rows, uint32_t w, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const double* __restrict__ dinv, const double* rin, double* rout,
+                                                   const float* __restrict__ y, const double* acc_in,
+                                                   const float* __restrict__ y0, double* acc_out, double inv_theta,
+                                                   float* __restrict__ r32, float* __restrict__ ynext) {
+  __shared__ int32_t s_col[STAGE_CAP];
+  __shared__ double s_val[STAGE_CAP];
+  const uint32_t wl = w / V;
+  const uint32_t g = lane_id();
+  auto sg = stage_rows<double, 1>(rp, col, val, rows, wl, s_col, s_val);
+  if (g >= rows * wl) return;
+  const uint32_t row = g / wl, e = (g - row * wl) * V;
+  const size_t o = (size_t)row * w + e;
+  const Vx<double, V> ri = ldv<double, V>(rin + o);
+  const int32_t k0 = rp[row], k1 = rp[row + 1];
+  const Vx<double, V> s = sg.ok ? row_spmv<double, V, 8, float>(s_col, s_val, sg.kbeg, k0, k1, y, w, e)
+                                : row_spmv<double, V, 8, float>(col, val, 0, k0, k1, y, w, e);
+  const double sc = dinv[row] * inv_theta;
+  Vx<double, V> r;
+  Vx<float, V> r3, yn;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    r.v[i] = ri.v[i] - s.v[i];
+    r3.v[i] = (float)r.v[i];
+    yn.v[i] = (float)(sc * r.v[i]);
+  }
+  if (rout) stv<double, V>(rout + o, r);
+  stv<float, V>(r32 + o, r3);
+  stv<float, V>(ynext + o, yn);
+  if (acc_out) stv<double, V>(acc_out + o, pass_sum<V>(acc_in, y0, ldv<float, V>(y + o), o));
+}
+
+// after the last pass: z = pass_sum (FP64), then as the last step of the
+// FP64 solve: mode 0 out = z; mode 1 the filter update of k_cj_step
+template <int V>
+__global__ __launch_bounds__(256) void k_mix_final(uint32_t rows, uint32_t w, const double* __restrict__ acc_in,
+                                                   const float* __restrict__ y0, const float* __restrict__ y,
+                                                   int mode, double* out, const double* __restrict__ win,
+                                                   const double* wprev, double a1, double cs, double a2, int ymode,
+                                                   double mu0, double mu, const double* __restrict__ mu0c,
+                                                   const double* __restrict__ muc, double* wout, double* Yacc) {
+  const uint32_t wl = w / V;
+  const uint32_t g = lane_id();
+  if (g >= rows * wl) return;
+  const uint32_t row = g / wl, e = (g - row * wl) * V;
+  const size_t o = (size_t)row * w + e;
+  const Vx<double, V> z = pass_sum<V>(acc_in, y0, ldv<float, V>(y + o), o);
+  if (mode == 0) {
+    stv<double, V>(out + o, z);
+    return;
+  }
+  const Vx<double, V> wi = ldv<double, V>(win + o);
+  Vx<double, V> wo;
+#pragma unroll
+  for (int i = 0; i < V; ++i) wo.v[i] = a1 * (z.v[i] - cs * wi.v[i]);
+  if (a2 != 0.0) {
+    const Vx<double, V> wp = ldv<double, V>(wprev + o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) wo.v[i] += a2 * wp.v[i];
+  }
+  stv<double, V>(wout + o, wo);
+  if (ymode == 0) return;
+  double m0[V], m1[V];
+  series_coef<double, V>(mu0, mu, mu0c, muc, e % (w / 3), m0, m1);
+  if (ymode == 1) {
+    Vx<double, V> yy;
+#pragma unroll
+    for (int i = 0; i < V; ++i) yy.v[i] = m0[i] * wi.v[i] + m1[i] * wo.v[i];
+    stv<double, V>(Yacc + o, yy);
+  } else if (ymode == 2) {
+    Vx<double, V> yy = ldv<double, V>(Yacc + o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) yy.v[i] += m1[i] * wo.v[i];
+    stv<double, V>(Yacc + o, yy);
+  }
+}
+
 template <class T>
 __global__ void k_scale_copy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
   int64_t g = gtid();
@@ -679,8 +831,10 @@ template <class T>
 void launch_apply_ag(int64_t N, int b, const int32_t* rp, const int32_t* col, const T* ag, const T* X,
                      const int32_t* egp, const int32_t* egc, const T* egv, const T* S, T* F, const T* dinv,
                      T inv_theta, T* Y1, hipStream_t st) {
-  int v = pick_v<T>(b);
-  NM_LAUNCH_V(k_apply_ag, T, v, N * (3 * b / v), st, (uint32_t)N, (uint32_t)b, rp, col, ag, X, egp, egc, egv, S, F,
+  // two entries per lane (8- or 16-byte gathers): b / 2 lanes per row keeps a
+  // workgroup's rows within the LDS stage at 32 columns
+  const int v = b % 2 == 0 ? 2 : 1;
+  NM_LAUNCH_V(k_apply_ag, T, v, N * (b / v), st, (uint32_t)N, (uint32_t)b, rp, col, ag, X, egp, egc, egv, S, F,
               dinv, inv_theta, Y1);
 }
 
@@ -764,11 +918,84 @@ struct Update {
   const void* muc = nullptr;
 };
 
+// Mixed-precision mass solve: Z = S(f) (mode 0) or the filter update u with
+// z = S(f), by cfg.mixP FP32 passes of cfg.mixK Chebyshev-Jacobi steps (see
+// k_mix_first).  Uses w.ya (FP64 residual), w.yb (FP64 sum) and w.s0..s3.
+void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, const Update& u, const ApplyCfg& cfg,
+                      FilterWork<double>& w, hipStream_t st, KernelProf* prof) {
+  NM_REQUIRE(cfg.mixP >= 2 && cfg.mixK >= 2, NM_EINVAL, "mixed mass solve needs >= 2 passes of >= 2 steps");
+  NM_REQUIRE(P->ms32.p && P->mdinv32.p, NM_EINVAL, "mixed mass solve without the FP32 matrix shadows");
+  w.ensure_mixed(P, b);
+  const auto m64 = mats<double>(P);
+  const auto m32 = mats<float>(P);
+  const GroupPlan tp = group_plan<float>(P, b);
+  const ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, cfg.mixK);
+  const int64_t N = P->N;
+  const int wd = 3 * b;
+  const int v = wd % 4 == 0 ? 4 : (wd % 2 == 0 ? 2 : 1);
+  const int64_t lanes = N * (wd / v);
+  const double it = 1.0 / cc.theta;
+  // FP32 buffers: right-hand side, two iterates, and the first pass's result
+  // (kept in FP32 until the second pass's is added to it in FP64)
+  float *rhs = w.s0.p, *cur = w.s1.p, *prev = w.s2.p, *spare = w.s3.p, *y0 = nullptr;
+  double *r64 = w.ya.p, *acc = w.yb.p;
+#define NM_MIX(KERN, ...)                                                                      \
+  do {                                                                                         \
+    if (v == 4)                                                                                \
+      hipLaunchKernelGGL((KERN<4>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);      \
+    else if (v == 2)                                                                           \
+      hipLaunchKernelGGL((KERN<2>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);      \
+    else                                                                                       \
+      hipLaunchKernelGGL((KERN<1>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);      \
+  } while (0)
+  const int P_ = cfg.mixP;
+  NM_MIX(k_mix_first, (uint32_t)N, (uint32_t)wd, m64.mdinv, f, it, rhs, cur);
+  for (int p = 0; p < P_; ++p) {
+    for (int j = 1; j < cfg.mixK; ++j) {
+      bool sampled = false;
+      if (prof && j >= 2) prof->before(st, sampled);
+      launch_cj_step<float>(N, wd, P->row_ptr.p, P->col.p, m32.ms, m32.mdinv, rhs, cur, prev, (float)cc.alpha[j - 1],
+                            (float)cc.beta[j - 1], j == 1 ? 1 : 0, 0, prev, nullptr, nullptr, 0.f, 0.f, 0.f, 0, 0.f,
+                            0.f, nullptr, nullptr, st, &tp);
+      if (sampled) prof->after(st);
+      std::swap(cur, prev);
+    }
+    if (p + 1 == P_) break;
+    // cur: this pass's result; prev receives the next pass's first iterate
+    NM_MIX(k_mix_resid, (uint32_t)N, (uint32_t)wd, P->row_ptr.p, P->col.p, m64.ms, m64.mdinv, p == 0 ? f : r64,
+           p + 2 < P_ ? r64 : nullptr, cur, p >= 2 ? acc : nullptr, p == 1 ? y0 : nullptr, p >= 1 ? acc : nullptr, it,
+           rhs, prev);
+    if (p == 0) {
+      y0 = cur;  // kept until the next residual adds it to acc
+      cur = prev;
+      prev = spare;
+    } else if (p == 1) {
+      spare = y0;
+      y0 = nullptr;
+      std::swap(cur, prev);
+    } else {
+      std::swap(cur, prev);
+    }
+  }
+  NM_MIX(k_mix_final, (uint32_t)N, (uint32_t)wd, P_ >= 3 ? acc : nullptr, P_ == 2 ? y0 : nullptr, cur,
+         u.on ? 1 : 0, Z, (const double*)u.win, (const double*)u.wprev, u.a1, u.cs, u.a2, u.ymode, u.mu0, u.mu,
+         (const double*)u.mu0c, (const double*)u.muc, (double*)u.wout, (double*)u.Y);
+#undef NM_MIX
+}
+
 // z = S_M(A X); either written to Z or consumed by the filter update u
 template <class T>
-void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, int kM, int kP, FilterWork<T>& w,
-                  hipStream_t st, KernelProf* prof = nullptr) {
+void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, const ApplyCfg& cfg,
+                  FilterWork<T>& w, hipStream_t st, KernelProf* prof = nullptr) {
+  const int kM = cfg.kM, kP = cfg.kP;
   NM_REQUIRE(kM >= 2, NM_EINVAL, "the M solve needs at least 2 Chebyshev steps");
+  if constexpr (std::is_same<T, double>::value) {
+    if (cfg.mixP > 0) {
+      a_apply<double>(P, b, X, w.f.p, nullptr, 0.0, kP, w, st);
+      mass_solve_mixed(P, b, w.f.p, Z, u, cfg, w, st, prof);
+      return;
+    }
+  }
   auto m = mats<T>(P);
   ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, kM);
   const GroupPlan tp = group_plan<T>(P, b);
@@ -818,10 +1045,31 @@ void FilterWork<T>::ensure(const nm_pencil* P, int ncols) {
 }
 
 template <class T>
+void FilterWork<T>::ensure_mixed(const nm_pencil* P, int ncols) {
+  ensure(P, ncols);
+  const size_t n = (size_t)P->N * 3 * ncols;
+  if (s0.n >= n && s0.p) return;
+  s0.alloc(n); s1.alloc(n); s2.alloc(n); s3.alloc(n);
+}
+
+void set_mass_passes(nm_pencil* P, ApplyCfg& cfg, int passes, double mtol, int kM_pass, hipStream_t st) {
+  cfg.mixP = 0;
+  cfg.mixK = 0;
+  if (passes == 0) return;
+  NM_REQUIRE(passes >= 2 && passes <= 8, NM_EINVAL, "mass_passes must be 0 or 2..8");
+  NM_REQUIRE(cfg.precision == 0, NM_EINVAL, "mass_passes applies to FP64 filters (precision 0)");
+  NM_REQUIRE(kM_pass > 0 || mtol > 0, NM_EINVAL, "mass_passes needs a bound or a step count");
+  cfg.mixP = passes;
+  cfg.mixK = kM_pass > 0 ? kM_pass : cheb_steps(P->ref.m_lo, P->ref.m_hi, std::pow(mtol, 1.0 / passes));
+  NM_REQUIRE(cfg.mixK >= 2, NM_EINVAL, "a mass-solve pass needs at least 2 steps");
+  P->ensure_fp32(st);
+}
+
+template <class T>
 void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
              hipStream_t st) {
   w.ensure(P, ncols);
-  b_apply_impl<T>(P, ncols, X, Y, Update{}, cfg.kM, cfg.kP, w, st);
+  b_apply_impl<T>(P, ncols, X, Y, Update{}, cfg, w, st);
 }
 
 // Y = p(B) X, or ((B - l0)/s0) p(B) X when s0 != 0; p = sum_k mu_k T_k((t - c)/e).
@@ -842,7 +1090,7 @@ static void filter_run(const nm_pencil* P, const double* mu, const T* MUd, int m
   if (s0 != 0.0) {
     Update u;
     u.on = true; u.win = X; u.a1 = 1.0 / s0; u.cs = l0; u.a2 = 0.0; u.ymode = 0; u.wout = bufs[0];
-    b_apply_impl<T>(P, ncols, X, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
+    b_apply_impl<T>(P, ncols, X, nullptr, u, cfg, w, st, cfg.prof);
     win = bufs[0];
     nb = 1;
     if (m == 0) {
@@ -863,7 +1111,7 @@ static void filter_run(const nm_pencil* P, const double* mu, const T* MUd, int m
       u.mu = mu[1];
     }
     u.wout = bufs[nb]; u.Y = Y;
-    b_apply_impl<T>(P, ncols, win, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
+    b_apply_impl<T>(P, ncols, win, nullptr, u, cfg, w, st, cfg.prof);
     wprev = win;
     win = bufs[nb];
     nb ^= 1;
@@ -878,7 +1126,7 @@ static void filter_run(const nm_pencil* P, const double* mu, const T* MUd, int m
     else
       u.mu = mu[k];
     u.wout = out; u.Y = Y;
-    b_apply_impl<T>(P, ncols, win, nullptr, u, cfg.kM, cfg.kP, w, st, cfg.prof);
+    b_apply_impl<T>(P, ncols, win, nullptr, u, cfg, w, st, cfg.prof);
     wprev = win;
     win = out;
     nb = (out == bufs[0]) ? 1 : 0;
@@ -1034,6 +1282,14 @@ static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* 
       break;
     }
     case NM_OP_MINV: {
+      if constexpr (std::is_same<T, double>::value) {
+        if (cfg.mixP > 0) {
+          FilterWork<double> w;
+          mass_solve_mixed(P, b, X, Y, Update{}, cfg, w, st, nullptr);
+          NM_HIP(hipStreamSynchronize(st));
+          break;
+        }
+      }
       NM_REQUIRE(cfg.kM >= 2, NM_EINVAL, "kM must be >= 2");
       DBuf<T> ya(N * wd), yb(N * wd);
       ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, cfg.kM);

@@ -72,13 +72,14 @@ double request_bytes(const nm_mesh& m, int S, const int32_t* nev, const nm_eig_o
   const double N = p2 ? 2.0 * V + T : V, n = 3.0 * N;
   const double nnzb = (p2 ? 28.0 : 15.0) * N;
   double bytes = nnzb * (72.0 + 8.0 + 4.0) + nnzb * 0.6 * 4.0 * 8.0;
-  if (o.precision == 1) bytes += nnzb * (36.0 + 4.0);
+  if (o.precision == 1 || o.mass_passes) bytes += nnzb * (36.0 + 4.0);
   const double nd = p2 ? 10.0 : 4.0;
   bytes = std::max(bytes, T * nd * nd * 9.0 * 8.0 * 1.5);
   const int bs = o.block > 0 ? o.block : 16;
   for (int i = 0; i < S; ++i) {
     const double K = std::max({6.0 * nev[i], nev[i] + 16.0 * bs, 320.0});
     bytes += 2.0 * K * n * 8.0 + 8.0 * n * bs * 8.0 + 6.0 * n * 3.0 * nev[i] * 8.0;
+    if (o.mass_passes) bytes += 3.0 * n * bs * 4.0;
   }
   return bytes;
 }

@@ -122,6 +122,8 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
   cfg.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, mtol);
   cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, ptol);
   cfg.precision = prec;
+  // before the slice threads start: creates the FP32 shadows the mixed solve reads
+  set_mass_passes(const_cast<nm_pencil*>(P), cfg, o.mass_passes, mtol, 0, st);
   FilterBatcher fb(P, prec, cfg, 0.5 * (lmax + lmin), 0.5 * (lmax - lmin), S, st);
 
   std::vector<std::exception_ptr> errs(S);
@@ -165,7 +167,7 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
     out[i]->hot_launches = fb.prof.launches;
     out[i]->hot_samples = fb.prof.samples;
     out[i]->hot_ms = fb.prof.samples ? fb.prof.ms / fb.prof.samples : 0.0;
-    const double sz = prec ? 4.0 : 8.0;
+    const double sz = (prec || cfg.mixP) ? 4.0 : 8.0;
     out[i]->hot_bytes = (double)P->nnzb * (4.0 + sz) + 4.0 * (P->N + 1) + sz * P->N + 4.0 * 3 * P->N * ctot * sz;
   }
   for (int i = 0; i < S; ++i)

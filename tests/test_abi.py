@@ -81,3 +81,37 @@ def test_filter_degree_upper_only_is_cheaper(lib):
     m0 = nm.filter_degree(1, 60, 0, 3e4, 0.5, 0)
     m1 = nm.filter_degree(1, 60, 0, 3e4, 0.5, 1)
     assert m0 < m1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's field
+    offsets and sizes (a field added to one side only shifts every later one)."""
+    import shutil
+    import subprocess
+    import paper_1906_11082_amd as nm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    rename = {"_EigResult": {"lam": "lambda"}}
+    structs = [(nm._Mesh, "nm_mesh"), (nm._Material, "nm_material"), (nm._Info, "nm_pencil_info"),
+               (nm._ApplyOpts, "nm_apply_opts"), (nm._EigOpts, "nm_eig_opts"), (nm._EigResult, "nm_eig_result"),
+               (nm._RotResult, "nm_rot_result"), (nm._Request, "nm_request"),
+               (nm._ServerResult, "nm_server_result")]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "nmodes.h"', "int main(void) {"]
+    want = []
+    for cls, cname in structs:
+        lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        want.append(("sizeof", cname, C.sizeof(cls)))
+        for f in cls._fields_:
+            name = rename.get(cls.__name__, {}).get(f[0], f[0])
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, name))
+            want.append((cname, name, getattr(cls, f[0]).offset))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert len(got) == len(want)
+    for (a, b, w), g in zip(want, got):
+        assert g == w, (a, b, w, g)
