@@ -948,9 +948,9 @@ void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, con
     else                                                                                       \
       hipLaunchKernelGGL((KERN<1>), dim3(grid_for(lanes)), dim3(256), 0, st, __VA_ARGS__);      \
   } while (0)
-  const int P_ = cfg.mixP;
+  const int passes = cfg.mixP;
   NM_MIX(k_mix_first, (uint32_t)N, (uint32_t)wd, m64.mdinv, f, it, rhs, cur);
-  for (int p = 0; p < P_; ++p) {
+  for (int p = 0; p < passes; ++p) {
     for (int j = 1; j < cfg.mixK; ++j) {
       bool sampled = false;
       if (prof && j >= 2) prof->before(st, sampled);
@@ -960,11 +960,11 @@ void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, con
       if (sampled) prof->after(st);
       std::swap(cur, prev);
     }
-    if (p + 1 == P_) break;
+    if (p + 1 == passes) break;
     // cur: this pass's result; prev receives the next pass's first iterate
     NM_MIX(k_mix_resid, (uint32_t)N, (uint32_t)wd, P->row_ptr.p, P->col.p, m64.ms, m64.mdinv, p == 0 ? f : r64,
-           p + 2 < P_ ? r64 : nullptr, cur, p >= 2 ? acc : nullptr, p == 1 ? y0 : nullptr, p >= 1 ? acc : nullptr, it,
-           rhs, prev);
+           p + 2 < passes ? r64 : nullptr, cur, p >= 2 ? acc : nullptr, p == 1 ? y0 : nullptr,
+           p >= 1 ? acc : nullptr, it, rhs, prev);
     if (p == 0) {
       y0 = cur;  // kept until the next residual adds it to acc
       cur = prev;
@@ -977,7 +977,7 @@ void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, con
       std::swap(cur, prev);
     }
   }
-  NM_MIX(k_mix_final, (uint32_t)N, (uint32_t)wd, P_ >= 3 ? acc : nullptr, P_ == 2 ? y0 : nullptr, cur,
+  NM_MIX(k_mix_final, (uint32_t)N, (uint32_t)wd, passes >= 3 ? acc : nullptr, passes == 2 ? y0 : nullptr, cur,
          u.on ? 1 : 0, Z, (const double*)u.win, (const double*)u.wprev, u.a1, u.cs, u.a2, u.ymode, u.mu0, u.mu,
          (const double*)u.mu0c, (const double*)u.muc, (double*)u.wout, (double*)u.Y);
 #undef NM_MIX

@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-active", type=int, default=4)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--mass-passes", type=int, default=0,
+                    help="FP64 filters: mass solves as this many FP32 passes with FP64 residual corrections")
     ap.add_argument("--seed", type=int, default=4)
     args = ap.parse_args()
     import numpy as np
@@ -73,7 +75,8 @@ def main():
             time.sleep(delay)
         sub = time.perf_counter() - t0
         tickets.append((r, sub, server.submit(planet, r["windows"], r["nev"], args.tol, rotate=r["omega"] > 0,
-                                              precision=prec, block=16, verbose=1)))
+                                              precision=prec, block=16, verbose=1,
+                                              mass_passes=0 if prec else args.mass_passes)))
         print("[serve] submitted request %d (T=%d, P%d, %d windows) at %.2fs"
               % (len(tickets) - 1, len(planet["tet"]), r["order"], len(r["windows"]), sub), file=sys.stderr,
               flush=True)

@@ -167,23 +167,26 @@ def test_empty_window_returns_no_pairs():
     assert r.count == 0
 
 
-def test_slices_batched_equal_alone():
+@pytest.mark.parametrize("mass_passes", [0, 2])
+def test_slices_batched_equal_alone(mass_passes):
     """Spectrum slicing with shared filter applications: two windows solved
     together (one Lanczos per window, their filter blocks concatenated with
     one Chebyshev series per column) give bit-identical eigenvalues to each
-    window solved alone with the same bounds and start block."""
+    window solved alone with the same bounds and start block; also with the
+    mass solve in FP32 passes."""
     import paper_1906_11082_amd as nm
     d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
-    print("\n[case] slices layered P2/P1 n_half=4", flush=True)
+    print("\n[case] slices layered P2/P1 n_half=4, mass_passes %d" % mass_passes, flush=True)
     G = nm.Pencil(d)
     lo, hi = G.spectrum_bounds()
     lmin, lmax = lo - 0.01, hi
     wins = [(1.0, 6.0), (6.0, 12.0)]
-    rs = G.filtered_eig_slices(wins, 100, 1e-9, block=8, lmin=lmin, lmax=lmax, seed=7)
+    rs = G.filtered_eig_slices(wins, 100, 1e-9, block=8, lmin=lmin, lmax=lmax, seed=7, mass_passes=mass_passes)
     assert len(rs) == 2
     for i, (a, b) in enumerate(wins):
         seed_i = (7 + 0x9E3779B97F4A7C15 * (i + 1)) % (1 << 64)
-        r1 = G.filtered_eig(a, b, 100, 1e-9, block=8, lmin=lmin, lmax=lmax, seed=seed_i)
+        r1 = G.filtered_eig(a, b, 100, 1e-9, block=8, lmin=lmin, lmax=lmax, seed=seed_i, mass_passes=mass_passes)
+        assert r1.stats["mass_passes"] == rs[i].stats["mass_passes"] == mass_passes
         print("slice %d: %d pairs, batched degree %d, alone degree %d" % (i, r1.count, rs[i].stats["degree"],
                                                                         r1.stats["degree"]), flush=True)
         assert r1.count == rs[i].count > 0
