@@ -153,7 +153,7 @@ def main():
     traffic = None
     # the sampled kernel: a middle step of the FP64 mass solve, or of an FP32 pass
     hot_prec = "fp32" if prec else ("mixed" if args.mass_passes else "fp64")
-    hot = "k_cj_group" if 3 * st["block"] * (8 if hot_prec == "fp64" else 4) >= 768 else "k_cj_step"
+    hot = "k_cj_group" if st["block"] >= 32 else "k_cj_step"
     if not args.traffic_json:
         args.traffic_json = os.path.join(ROOT, "profiles", "%s_c2_%s_b%d_traffic.json" % (hot, hot_prec,
                                                                                            st["block"]))

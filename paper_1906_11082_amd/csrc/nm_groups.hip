@@ -114,7 +114,7 @@ __global__ void k_group_coef(int64_t N, int R, const int32_t* __restrict__ rp, c
 }
 
 void build_row_groups(nm_pencil* P, hipStream_t st) {
-  // NM_ROW_GROUPS: 0 per-row kernel only, 1 (default) grouped for rows of >= 768 bytes, 2 grouped at any width
+  // NM_ROW_GROUPS: 0 per-row kernel only, 1 (default) grouped from 32 columns, 2 grouped at any width
   const char* env = getenv("NM_ROW_GROUPS");
   P->grouped = env ? atoi(env) : 1;
   if (P->grouped <= 0) {

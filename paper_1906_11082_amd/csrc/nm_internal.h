@@ -145,7 +145,7 @@ struct nm_pencil {
   nm::DBuf<int32_t> grp_ptr, grp_col;
   nm::DBuf<double> grp_coef;
   nm::DBuf<float> grp_coef32;  // FP32 shadow (built with the other FP32 shadows)
-  int grouped = 1;  // 0: per-row kernels only; 1: grouped for rows of >= 768 bytes; 2: grouped at any width
+  int grouped = 1;  // 0: per-row kernels only; 1: grouped from 32 columns; 2: grouped at any width
   int tuned_block = 0;  // block width chosen by the autotuner (0: none)
   rocblas_handle blas = nullptr;
   void ensure_fp32(hipStream_t st);

@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_cj_group(
     const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
     T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
     T* Yacc) {
-  constexpr int GCAP = 640;
+  constexpr int GCAP = sizeof(T) == 8 ? 640 : 1280;  // about 23-26 KB of LDS either way
   __shared__ int32_t s_col[GCAP];
   __shared__ T s_cf[GCAP * R];
   const uint32_t wl = w / V;
@@ -773,16 +773,16 @@ struct GroupPlan {
   const int32_t *gptr = nullptr, *gcol = nullptr;
   const void* gcoef = nullptr;
 };
-// By default only for rows of at least 768 bytes (FP64 from 32 columns, FP32
-// from 64): narrower rows put more groups in a workgroup than its LDS stage
-// holds, and measured slower than the per-row kernel (FP32, 32 columns: 0.45
-// vs 0.42 ms; 64 columns: 0.63 vs 0.78 ms).  grouped == 2 forces the grouped
-// kernel at any width.
+// By default only for blocks of at least 32 columns: narrower rows put more
+// groups in a workgroup than its LDS stage holds (640 union entries in FP64,
+// 1280 in FP32).  FP32 at 32 columns on the 384k-tet planet: 0.353 vs
+// 0.422 ms (grouped vs per-row).  grouped == 2 forces the grouped kernel at
+// any width.
 template <class T>
 GroupPlan group_plan(const nm_pencil* P, int b) {
   GroupPlan tp;
   if (!P->grouped || P->grp_rows <= 0 || b < 1) return tp;
-  if (P->grouped == 1 && 3 * (size_t)b * sizeof(T) < 768) return tp;
+  if (P->grouped == 1 && b < 32) return tp;
   const void* cf = sizeof(T) == 8 ? (const void*)P->grp_coef.p : (const void*)P->grp_coef32.p;
   if (!cf) return tp;
   tp.on = true;

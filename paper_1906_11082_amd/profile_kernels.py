@@ -6,15 +6,15 @@
 
 Launches, on the three-layer planet at n_half (default 20): `reps` M-solves
 of `steps` Chebyshev-Jacobi steps on a block of `block` columns (so the
-middle-step kernel dominates: k_cj_group for rows of 768 bytes or more --
-FP64 from 32 columns, FP32 from 64 -- and k_cj_step otherwise), one filter application of degree `degree`, and a
+middle-step kernel dominates: k_cj_group from 32 columns, k_cj_step for
+narrower blocks), one filter application of degree `degree`, and a
 plain device copy of `copy_mb` MB (torch) that calibrates the HBM byte
 counters.  Prints the algorithmic bytes of one middle-step launch so the
 counters can be compared with it.
 
 --mass-passes P (FP64 vectors): the M solves and the filter's M solves run as
 P FP32 passes of `steps` (filter: 22) steps with FP64 residual corrections,
-so the middle-step kernel is the FP32 one (k_cj_step for 32 columns) next to
+so the middle-step kernel is the FP32 one (k_cj_group at 32 columns) next to
 k_mix_first, k_mix_resid and k_mix_final.
 """
 import argparse

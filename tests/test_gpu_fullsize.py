@@ -77,13 +77,38 @@ def test_mass_solve_within_chebyshev_bound(full):
 
 def test_row_groups_match_per_row_at_full_size(full, monkeypatch):
     """The benchmark's row-group kernel and the per-row kernel give bit-identical
-    mass solves and filter applications on the full planet at 32 columns."""
+    mass solves (FP64 and FP32) and filter applications on the full planet at
+    32 columns."""
     torch, nm, d, G = full
     monkeypatch.setenv("NM_ROW_GROUPS", "0")
     Gr = nm.Pencil(d)
     n = G.info["n_disp"]
     X = _rand(torch, n, 32, 4)
     assert torch.equal(G.apply(nm.OP_MINV, X, kM=12), Gr.apply(nm.OP_MINV, X, kM=12))
+    X32 = X.float()
+    assert torch.equal(G.apply(nm.OP_MINV, X32, kM=12, precision=1), Gr.apply(nm.OP_MINV, X32, kM=12, precision=1))
     mu = nm.filter_coeffs(1.0, 60.0, -4.0, 7.2e5, 6)
     c, e = 0.5 * (7.2e5 - 4.0), 0.5 * (7.2e5 + 4.0)
     assert torch.equal(G.filter_apply(mu, c, e, X, kM=8, kP=6), Gr.filter_apply(mu, c, e, X, kM=8, kP=6))
+
+
+def test_mixed_mass_solve_at_full_size(full):
+    """The benchmark's mass solve (2 FP32 passes of 22 steps, row-group kernel,
+    32 columns) equals y = S f + S (f - M S f) with the 22-step FP64 solve S up
+    to FP32 rounding of the second pass's correction (1e-5 of the pass factor
+    2 r^22), and M^-1 f within the bound (2 r^22)^2."""
+    torch, nm, d, G = full
+    n = G.info["n_disp"]
+    F = _rand(torch, n, 32, 5)
+    Y = G.apply(nm.OP_MINV, F, kM=22, mass_passes=2)
+    y = G.apply(nm.OP_MINV, F, kM=22)
+    y = y + G.apply(nm.OP_MINV, F - G.apply(nm.OP_M, y), kM=22)
+    kap = G.info["minv_hi"] / G.info["minv_lo"]
+    fac = 2 * ((np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)) ** 22
+    rel = ((Y - y).norm(dim=0) / y.norm(dim=0)).max().item()
+    exact = G.apply(nm.OP_MINV, F, kM=80)
+    err = ((Y - exact).norm(dim=0) / exact.norm(dim=0)).max().item()
+    print("full-size mixed solve: |mixed - fp64 refinement| %.2e, |mixed - M^-1 f| %.2e (factor %.2e)"
+          % (rel, err, fac), flush=True)
+    assert rel <= 1e-5 * fac
+    assert err <= 100 * fac ** 2
