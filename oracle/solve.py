@@ -5,7 +5,9 @@
 * The paper accesses A, M and M^{-1} only through matrix-vector products
   (Sec. 6.1).  M^{-1} here: Chebyshev iteration preconditioned by the
   diagonal of M, on the interval that bounds the spectrum of D^{-1} M
-  element by element (the same iteration serves K_p^{-1}).
+  element by element (the same iteration serves K_p^{-1}); its iterative
+  refinement y <- y + S(f - M y) over several passes, in float64 or with
+  float32 passes (the library's mass_passes).
 * Polynomial filtering (Sec. 2.5 remark, Sec. 6.1): a Jackson-damped
   Chebyshev expansion of the indicator of the window, applied by the
   three-term recurrence, optionally times the factor (B - lambda_0)/s that
@@ -58,6 +60,28 @@ def cheb_jacobi(Mop, diag, f, k, lo, hi):
         d = rho_new * rho * d + (2.0 * rho_new / delta) * dinv * r
         rho = rho_new
     return x
+
+
+def cheb_jacobi_refined(Mop, diag, f, k, lo, hi, passes, Mop32=None):
+    """Iterative refinement of the k-step solve S = cheb_jacobi: from y = 0,
+    `passes` times y <- y + S(f - M y), so M^{-1} f - y = (I - S M)^passes M^{-1} f.
+    The paper fixes only that M^{-1} is applied through products with M
+    (Sec. 6.1); this is the reading the library's mass_passes option computes.
+    With Mop32 (M in float32) each S runs in float32 on the float32-rounded
+    residual while the residuals and the sum stay float64, as the library's
+    passes do (a model of their rounding, not of their summation order)."""
+    y = np.zeros_like(f)
+    r = f.copy()
+    for p in range(passes):
+        if Mop32 is None:
+            d = cheb_jacobi(Mop, diag, r, k, lo, hi)
+        else:
+            d = cheb_jacobi(Mop32, diag.astype(np.float32), r.astype(np.float32), k,
+                            np.float32(lo), np.float32(hi)).astype(np.float64)
+        y = y + d
+        if p + 1 < passes:
+            r = f - Mop(y)
+    return y
 
 
 # ------------------------------------------------------------------ filter

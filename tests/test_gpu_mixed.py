@@ -51,6 +51,30 @@ def test_mixed_solve_is_the_refinement_of_the_fp64_solve(layered, passes, k, nco
     assert err <= 100 * fac ** passes
 
 
+def test_mixed_solve_matches_oracle_refinement(layered):
+    """The GPU passes against the oracle's refinement of its own Chebyshev-Jacobi
+    solve on the same planet and right-hand sides: within 1e-5 of the pass
+    factor of the FP64 definition (the FP32 rounding of the second pass's
+    correction), and as close to the oracle's float32-pass model."""
+    torch, nm, d, G = layered
+    from oracle.assemble import Pencil as OPencil
+    from oracle import solve as S
+    O = OPencil(d)
+    lo, hi = S.jacobi_mass_bounds(2)
+    assert abs(lo - G.info["minv_lo"]) <= 1e-14 and abs(hi - G.info["minv_hi"]) <= 1e-12
+    F = np.random.default_rng(11).standard_normal((O.n, 8))
+    Y = G.apply(nm.OP_MINV, torch.from_numpy(F).cuda(), kM=12, mass_passes=2).cpu().numpy()
+    dg = np.repeat(O.Ms.diagonal(), 3)
+    ref = S.cheb_jacobi_refined(lambda x: O.M @ x, dg, F, 12, lo, hi, 2)
+    M32 = O.M.astype(np.float32)
+    ref32 = S.cheb_jacobi_refined(lambda x: O.M @ x, dg, F, 12, lo, hi, 2, Mop32=lambda x: M32 @ x)
+    fac = 2 * _rate(G) ** 12
+    rel = (np.linalg.norm(Y - ref, axis=0) / np.linalg.norm(ref, axis=0)).max()
+    rel32 = (np.linalg.norm(Y - ref32, axis=0) / np.linalg.norm(ref, axis=0)).max()
+    print("oracle: |gpu - fp64 refinement| %.2e, |gpu - float32-pass model| %.2e" % (rel, rel32), flush=True)
+    assert rel <= 1e-5 * fac and rel32 <= 1e-5 * fac
+
+
 def test_mixed_filter_matches_fp64_filter(layered):
     """A degree-8 filter with the mixed solve (2 passes of 20 steps, bound
     1.3e-8) against the FP64 filter with a 90-step FP64 solve."""

@@ -47,6 +47,57 @@ def test_cheb_jacobi_error_bound(order, tol):
     assert abs(f[:, 0] @ Sx[:, 1] - f[:, 1] @ Sx[:, 0]) < 1e-13 * np.abs(f[:, 0] @ Sx[:, 0])
 
 
+@pytest.mark.parametrize("passes,k", [(2, 12), (3, 8)])
+def test_refined_mass_solve_error_operator_and_bound(passes, k):
+    """Refinement y <- y + S(f - M y) of the k-step solve S: the error after P
+    passes is (I - S M)^P applied to M^{-1} f (the error propagated pass by pass
+    from the exact solution, not through residuals), its M-norm is at most
+    (2 r^k)^P of that of M^{-1} f (I - S M is a polynomial in D^{-1} M,
+    self-adjoint in the M-inner product, of norm <= 2 r^k), and the passes in
+    float32 with float64 residuals stay within float32 rounding of the last
+    correction, 1e-5 (2 r^k)^(P-1), of the float64 refinement."""
+    P = pencil("three_layer_planet", n_half=4, order=2)
+    lo, hi = S.jacobi_mass_bounds(2)
+    d = np.repeat(P.Ms.diagonal(), 3)
+    Mop = lambda x: P.M @ x
+    M32 = P.M.astype(np.float32)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((P.n, 3))
+    xs = spla.splu(P.M.tocsc()).solve(f)
+    y = S.cheb_jacobi_refined(Mop, d, f, k, lo, hi, passes)
+    e = xs.copy()
+    for _ in range(passes):
+        e = e - S.cheb_jacobi(Mop, d, Mop(e), k, lo, hi)
+    mn = lambda v: np.sqrt(np.einsum("ij,ij->j", v, P.M @ v))
+    assert np.all(mn((xs - y) - e) <= 1e-12 * mn(xs))
+    kap = hi / lo
+    fac = 2 * ((math.sqrt(kap) - 1) / (math.sqrt(kap) + 1)) ** k
+    assert np.all(mn(xs - y) <= fac ** passes * mn(xs))
+    # one pass is the plain solve
+    assert np.array_equal(S.cheb_jacobi_refined(Mop, d, f, k, lo, hi, 1), S.cheb_jacobi(Mop, d, f, k, lo, hi))
+    y32 = S.cheb_jacobi_refined(Mop, d, f, k, lo, hi, passes, Mop32=lambda x: M32 @ x)
+    rel = np.linalg.norm(y32 - y, axis=0) / np.linalg.norm(y, axis=0)
+    assert np.all(rel <= 1e-5 * fac ** (passes - 1))
+
+
+def test_refined_float32_passes_beat_float32_rounding():
+    """At the benchmark's setting (2 passes of 22 steps, bound 1.8e-9) the
+    float32 passes reach the float64 bound, while one float32 solve of 44
+    steps stops at float32 rounding."""
+    P = pencil("three_layer_planet", n_half=4, order=2)
+    lo, hi = S.jacobi_mass_bounds(2)
+    d = np.repeat(P.Ms.diagonal(), 3)
+    M32 = P.M.astype(np.float32)
+    f = np.random.default_rng(4).standard_normal((P.n, 2))
+    xs = spla.splu(P.M.tocsc()).solve(f)
+    y32 = S.cheb_jacobi_refined(lambda x: P.M @ x, d, f, 22, lo, hi, 2, Mop32=lambda x: M32 @ x)
+    one32 = S.cheb_jacobi(lambda x: M32 @ x, d.astype(np.float32), f.astype(np.float32), 44,
+                          np.float32(lo), np.float32(hi)).astype(np.float64)
+    e_ref = np.linalg.norm(y32 - xs, axis=0) / np.linalg.norm(xs, axis=0)
+    e_one = np.linalg.norm(one32 - xs, axis=0) / np.linalg.norm(xs, axis=0)
+    assert np.all(e_ref <= 1e-8) and np.all(e_one >= 1e-8) and np.all(e_one > 10 * e_ref)
+
+
 # -------------------------------------------------------------------- filter
 def test_jackson_and_window_coefficients():
     g = S.jackson(30)
