@@ -20,6 +20,10 @@
  *   than requested, negative values are errors (NM_E*).  nm_last_error()
  *   returns a message for the last failing call on the calling thread.
  * - Host arrays passed in are borrowed for the duration of the call only.
+ * - Threads: different pencils may be used from different host threads at
+ *   once; calls on one pencil must not overlap (they share its rocBLAS
+ *   handle), except inside nm_filtered_eig_slices, which runs its windows
+ *   on threads of its own, each with its own stream and rocBLAS handle.
  * - Device arrays are plain device pointers (hipMalloc'd or from any
  *   allocator in the same process), row-major [rows][ncols] with the ncols
  *   columns of a row contiguous.  A displacement block therefore is

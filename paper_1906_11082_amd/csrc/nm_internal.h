@@ -148,6 +148,7 @@ struct nm_pencil {
   int grouped = 1;  // 0: per-row kernels only; 1: grouped from 32 columns; 2: grouped at any width
   int tuned_block = 0;  // block width chosen by the autotuner (0: none)
   rocblas_handle blas = nullptr;
+  std::mutex fp32_mx;  // the window threads of one pencil create the FP32 shadows once
   void ensure_fp32(hipStream_t st);
 };
 

@@ -918,14 +918,19 @@ struct Update {
   const void* muc = nullptr;
 };
 
+// work vectors of the mixed-precision mass solve, each [N][3b]
+struct MixBufs {
+  double *r64, *acc;  // FP64 residual, FP64 sum of the passes
+  float* s[4];        // FP32 right-hand side, two iterates, first pass's result
+};
+
 // Mixed-precision mass solve: Z = S(f) (mode 0) or the filter update u with
 // z = S(f), by cfg.mixP FP32 passes of cfg.mixK Chebyshev-Jacobi steps (see
-// k_mix_first).  Uses w.ya (FP64 residual), w.yb (FP64 sum) and w.s0..s3.
+// k_mix_first).
 void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, const Update& u, const ApplyCfg& cfg,
-                      FilterWork<double>& w, hipStream_t st, KernelProf* prof) {
+                      const MixBufs& w, hipStream_t st, KernelProf* prof) {
   NM_REQUIRE(cfg.mixP >= 2 && cfg.mixK >= 2, NM_EINVAL, "mixed mass solve needs >= 2 passes of >= 2 steps");
   NM_REQUIRE(P->ms32.p && P->mdinv32.p, NM_EINVAL, "mixed mass solve without the FP32 matrix shadows");
-  w.ensure_mixed(P, b);
   const auto m64 = mats<double>(P);
   const auto m32 = mats<float>(P);
   const GroupPlan tp = group_plan<float>(P, b);
@@ -937,8 +942,8 @@ void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, con
   const double it = 1.0 / cc.theta;
   // FP32 buffers: right-hand side, two iterates, and the first pass's result
   // (kept in FP32 until the second pass's is added to it in FP64)
-  float *rhs = w.s0.p, *cur = w.s1.p, *prev = w.s2.p, *spare = w.s3.p, *y0 = nullptr;
-  double *r64 = w.ya.p, *acc = w.yb.p;
+  float *rhs = w.s[0], *cur = w.s[1], *prev = w.s[2], *spare = w.s[3], *y0 = nullptr;
+  double *r64 = w.r64, *acc = w.acc;
 #define NM_MIX(KERN, ...)                                                                      \
   do {                                                                                         \
     if (v == 4)                                                                                \
@@ -991,8 +996,9 @@ void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, 
   NM_REQUIRE(kM >= 2, NM_EINVAL, "the M solve needs at least 2 Chebyshev steps");
   if constexpr (std::is_same<T, double>::value) {
     if (cfg.mixP > 0) {
+      w.ensure_mixed(P, b);
       a_apply<double>(P, b, X, w.f.p, nullptr, 0.0, kP, w, st);
-      mass_solve_mixed(P, b, w.f.p, Z, u, cfg, w, st, prof);
+      mass_solve_mixed(P, b, w.f.p, Z, u, cfg, MixBufs{w.ya.p, w.yb.p, {w.s0.p, w.s1.p, w.s2.p, w.s3.p}}, st, prof);
       return;
     }
   }
@@ -1284,8 +1290,10 @@ static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* 
     case NM_OP_MINV: {
       if constexpr (std::is_same<T, double>::value) {
         if (cfg.mixP > 0) {
-          FilterWork<double> w;
-          mass_solve_mixed(P, b, X, Y, Update{}, cfg, w, st, nullptr);
+          const size_t n = (size_t)N * wd;
+          DBuf<double> r64(n), acc(n);
+          DBuf<float> s0(n), s1(n), s2(n), s3(n);
+          mass_solve_mixed(P, b, X, Y, Update{}, cfg, MixBufs{r64.p, acc.p, {s0.p, s1.p, s2.p, s3.p}}, st, nullptr);
           NM_HIP(hipStreamSynchronize(st));
           break;
         }
@@ -1424,6 +1432,7 @@ void convert_f32_f64(int64_t n, const float* a, double* b, hipStream_t st) {
 }  // namespace nm
 
 void nm_pencil::ensure_fp32(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(fp32_mx);
   if (ms32.p) return;
   auto cv = [&](const nm::DBuf<double>& a, nm::DBuf<float>& b) {
     b.alloc(std::max<size_t>(a.n, 1));
