@@ -79,7 +79,7 @@ double request_bytes(const nm_mesh& m, int S, const int32_t* nev, const nm_eig_o
   for (int i = 0; i < S; ++i) {
     const double K = std::max({6.0 * nev[i], nev[i] + 16.0 * bs, 320.0});
     bytes += 2.0 * K * n * 8.0 + 8.0 * n * bs * 8.0 + 6.0 * n * 3.0 * nev[i] * 8.0;
-    if (o.mass_passes) bytes += 3.0 * n * bs * 4.0;
+    if (o.mass_passes) bytes += 4.0 * n * bs * 4.0;  // FP32 work vectors of the mixed mass solve
   }
   return bytes;
 }
