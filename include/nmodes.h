@@ -358,6 +358,21 @@ void nm_result_free(nm_eig_result* r);
 void nm_rot_result_free(nm_rot_result* r);
 void nm_pencil_free(nm_pencil* p);
 
+/* Device memory of the library's own buffers (pencil matrices, Krylov bases,
+ * work vectors) through the caller's allocator, e.g. a framework's caching
+ * allocator, instead of hipMalloc / hipFree; alloc == free_ == NULL restores
+ * those (NM_EINVAL if only one is NULL).  alloc(bytes, stream, ctx) returns
+ * device memory of the current device aligned to 256 bytes, or NULL (the
+ * call that needed it then fails with NM_ENOMEM); stream is NULL: the memory
+ * may be used on any stream.  free_(ptr, stream, ctx) is called after a
+ * device synchronisation, when no kernel uses the memory any more, with the
+ * functions and ctx that allocated it (a later change does not affect memory
+ * already allocated).  Result vectors (nm_eig_result.X, nm_rot_result.U)
+ * stay hipMalloc'd and are freed by nm_result_free / nm_rot_result_free.
+ * Call it while no other call of the library is in flight. */
+nm_status nm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                           void (*free_)(void* ptr, void* stream, void* ctx), void* ctx);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* nm_last_error(void);
 

@@ -29,7 +29,7 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_filtered_eig_slices", "nm_project_rotation", "nm_pencil_autotune", "nm_server_create",
             "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
-            "nm_pencil_free", "nm_last_error", "nm_version"]
+            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator"]
 
 
 class NMError(RuntimeError):
@@ -98,6 +98,12 @@ class _ServerResult(C.Structure):
 
 _lib = None
 
+# device allocator callbacks of nm_set_allocator
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+# every installed pair stays alive: memory it allocated is freed through it later
+_allocator_refs = []
+
 
 def library_path() -> str:
     return LIB_PATH
@@ -144,6 +150,7 @@ def load_library(path: str | None = None):
         "nm_pencil_free": ([P], None),
         "nm_last_error": ([], C.c_char_p),
         "nm_version": ([], C.c_char_p),
+        "nm_set_allocator": ([_ALLOC_FN, _FREE_FN, P], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -165,6 +172,30 @@ def _stream():
 
 def _ptr(a):
     return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(a.data_ptr())
+
+
+def set_allocator(alloc=None, free=None):
+    """Device buffers of the library through alloc(nbytes) -> device pointer
+    (int, 256-byte aligned, 0 on failure) and free(pointer), called after a
+    device synchronisation; both None restores hipMalloc / hipFree
+    (nm_set_allocator).  Call it while no library call is in flight."""
+    lib = load_library()
+    if alloc is None and free is None:
+        _check(lib.nm_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("set both allocator functions or neither")
+    a = _ALLOC_FN(lambda nbytes, stream, ctx: alloc(int(nbytes)) or None)
+    f = _FREE_FN(lambda ptr, stream, ctx: free(int(ptr)))
+    _allocator_refs.append((a, f))
+    _check(lib.nm_set_allocator(a, f, None))
+
+
+def use_torch_allocator():
+    """Device buffers of the library from torch's caching allocator, on the
+    device current now."""
+    dev = torch.cuda.current_device()
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device=dev), torch.cuda.caching_allocator_delete)
 
 
 def filter_coeffs(a, b, lmin, lmax, m):

@@ -22,6 +22,51 @@ std::vector<T> d2h(const T* d, size_t n) {
 }
 }  // namespace
 
+namespace nm {
+namespace {
+std::mutex g_alloc_mx;
+AllocHooks g_alloc;
+}  // namespace
+
+void set_alloc_hooks(const AllocHooks& h) {
+  std::lock_guard<std::mutex> lk(g_alloc_mx);
+  g_alloc = h;
+}
+
+void* dev_alloc(size_t bytes, AllocHooks* used) {
+  AllocHooks h;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mx);
+    h = g_alloc;
+  }
+  void* p = nullptr;
+  if (h.alloc) {
+    p = h.alloc(bytes, nullptr, h.ctx);
+    if (!p) throw Error(NM_ENOMEM, "the allocator set by nm_set_allocator returned NULL for " +
+                                       std::to_string(bytes) + " bytes");
+    if (((uintptr_t)p & 255u) != 0) {
+      h.free_(p, nullptr, h.ctx);
+      throw Error(NM_EINVAL, "the allocator set by nm_set_allocator returned memory not aligned to 256 bytes");
+    }
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    throw Error(NM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  *used = h;
+  return p;
+}
+
+void dev_free(void* p, const AllocHooks& used) noexcept {
+  if (used.free_) {
+    // the caller's allocator may hand the memory out again at once: no
+    // kernel of any stream may still use it
+    (void)hipDeviceSynchronize();
+    used.free_(p, nullptr, used.ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+}  // namespace nm
+
 static nm::ApplyCfg make_cfg(const nm_pencil* p, const nm_apply_opts* o, hipStream_t st) {
   nm::ApplyCfg c;
   double mt = (o && o->minv_tol > 0) ? o->minv_tol : 1e-12;
@@ -38,6 +83,18 @@ static nm::ApplyCfg make_cfg(const nm_pencil* p, const nm_apply_opts* o, hipStre
 extern "C" {
 
 const char* nm_last_error(void) { return nm::g_err.c_str(); }
+
+nm_status nm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                           void (*free_)(void* ptr, void* stream, void* ctx), void* ctx) {
+  NM_TRY({
+    NM_REQUIRE((alloc == nullptr) == (free_ == nullptr), NM_EINVAL, "set both allocator functions or neither");
+    nm::AllocHooks h;
+    h.alloc = alloc;
+    h.free_ = free_;
+    h.ctx = alloc ? ctx : nullptr;
+    nm::set_alloc_hooks(h);
+  })
+}
 const char* nm_version(void) { return "nmodes 0.1 (gfx950)"; }
 
 nm_status nm_assemble(const nm_mesh* mesh, const nm_material* mat, const double omega[3], void* stream,

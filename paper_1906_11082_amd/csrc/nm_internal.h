@@ -60,35 +60,42 @@ void set_error(const std::string& m);
     if (!(cond)) throw ::nm::Error(code, msg);                                          \
   } while (0)
 
+// Device allocator of the library's buffers (nm_set_allocator): the caller's
+// functions, or hipMalloc / hipFree when none are set.
+struct AllocHooks {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*free_)(void*, void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+void set_alloc_hooks(const AllocHooks& h);
+// allocates `bytes` with the current hooks and records them in *used (throws NM_ENOMEM)
+void* dev_alloc(size_t bytes, AllocHooks* used);
+// frees with the hooks that allocated p (caller's free after a device synchronisation)
+void dev_free(void* p, const AllocHooks& used) noexcept;
+
 // Owning device buffer.
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  AllocHooks h;  // the allocator that produced p
   DBuf() = default;
   explicit DBuf(size_t count) { alloc(count); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), h(o.h) { o.p = nullptr; o.n = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; h = o.h; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DBuf() { release(); }
   void alloc(size_t count) {
     release();
+    if (count) p = (T*)dev_alloc(count * sizeof(T), &h);
     n = count;
-    if (count) {
-      hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
-      if (e != hipSuccess) {
-        p = nullptr;
-        n = 0;
-        throw Error(NM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-      }
-    }
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, h);
     p = nullptr;
     n = 0;
   }

@@ -115,3 +115,15 @@ def test_struct_layouts_match_header(tmp_path):
     assert len(got) == len(want)
     for (a, b, w), g in zip(want, got):
         assert g == w, (a, b, w, g)
+
+
+def test_set_allocator_arguments(lib):
+    """nm_set_allocator takes both functions or neither (no device call is made)."""
+    import paper_1906_11082_amd as nm
+    a = nm._ALLOC_FN(lambda n, s, c: None)
+    assert lib.nm_set_allocator(a, nm._FREE_FN(), None) == -1
+    assert "both" in lib.nm_last_error().decode()
+    with pytest.raises(ValueError):
+        nm.set_allocator(alloc=lambda n: 0)
+    nm.set_allocator(None, None)
+    assert lib.nm_last_error().decode() == ""
