@@ -345,7 +345,11 @@ nm_status nm_server_destroy(nm_server* s);
 
 /* Rotating modes by projection on the non-rotating eigenvectors of basis
  * (Sec. 7, eqs. "linearpb", "sublinear0"): keeps omega > 0 with omega^2 in
- * [a, b].  Uses the pencil's Omega. */
+ * [a, b].  Uses the pencil's Omega.  The paper's setting (Sec. 3, eq.
+ * "freq") has the window far above |Omega| + (|Omega|^2 + max N^2)^(1/2),
+ * which with N^2 = 0 is 2 |Omega|, the top of the rotating fluid's
+ * continuous spectrum; the projection does not test this (the paper gives
+ * no threshold), so windows near 2 |Omega| are the caller's to avoid. */
 nm_status nm_project_rotation(const nm_pencil* p, const nm_eig_result* basis, double a, double b,
                               void* stream, nm_rot_result** out);
 
