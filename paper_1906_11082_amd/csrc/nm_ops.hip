@@ -15,6 +15,9 @@
 //   rho_0 = delta/theta, rho_j = 1 / (2 theta/delta - rho_{j-1}).
 // The last step of the M solve is fused with the three-term Chebyshev
 // filter update (W_{k+1} = a1 (B W_k - c W_k) + a2 W_{k-1}, Y += mu W_{k+1}).
+// With mass passes (ApplyCfg::mixP) the M solve of an FP64 filter runs as
+// FP32 passes of the same iteration joined by FP64 residual corrections
+// (mass_solve_mixed); the update is then fused into the final FP64 sum.
 #include <cmath>
 #include <cstdlib>
 #include <type_traits>
