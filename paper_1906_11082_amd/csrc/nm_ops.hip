@@ -560,13 +560,13 @@ __global__ __launch_bounds__(256) void k_cj_group(
 }
 
 // ---- mass solve in FP32 passes with FP64 residual corrections
-// (iterative refinement of the Chebyshev-Jacobi solve): pass 1 solves
-// M y_1 = f, pass p solves M y_p = r_{p-1} with r_p = r_{p-1} - M y_p formed
-// in FP64 from the FP32 result (which converts to FP64 exactly, so r_p carries
-// FP64 rounding only), and the solution y_1 + ... + y_P is summed in FP64.  With S the fixed-k solve,
-// the error operator is (I - S M)^P, so P passes of k steps reach the bound
-// (2 r^k)^P of one FP64 pass of P k steps, while rounding of each FP32 pass
-// is relative to the correction it computes.
+// (iterative refinement of the Chebyshev-Jacobi solve): with r_0 = f, pass p
+// solves M y_p = r_{p-1} in FP32 and r_p = r_{p-1} - M y_p is formed in FP64
+// from the FP32 result (which converts to FP64 exactly, so r_p carries FP64
+// rounding only); the solution y_1 + ... + y_P is summed in FP64.  With S the
+// fixed-k solve the error operator is (I - S M)^P, so P passes of k steps
+// reach the bound (2 r^k)^P of one FP64 pass of P k steps, while the rounding
+// of each FP32 pass is relative to the correction it computes.
 
 // pass 1, first iterate: f32 = f, y = D^{-1} f / theta (FP32)
 template <int V>
