@@ -336,7 +336,8 @@ nm_status nm_server_create(double hbm_budget_bytes, int32_t max_active, nm_serve
 /* Queue a request; *ticket identifies it for nm_server_wait. */
 nm_status nm_server_submit(nm_server* s, const nm_request* req, int64_t* ticket);
 /* Block until the request has finished; *out is freed with nm_server_result_free.
- * Each ticket can be waited for once. */
+ * Each ticket can be waited for once: a later (or concurrent) wait on the
+ * same ticket returns NM_EINVAL. */
 nm_status nm_server_wait(nm_server* s, int64_t ticket, nm_server_result** out);
 void nm_server_result_free(nm_server_result* r);
 /* Run every queued request to completion, then free the server (results not
@@ -376,6 +377,14 @@ void nm_pencil_free(nm_pencil* p);
  * Call it while no other call of the library is in flight. */
 nm_status nm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
                            void (*free_)(void* ptr, void* stream, void* ctx), void* ctx);
+
+/* Widest vector block the kernels accept for n_disp displacement rows: one
+ * launch indexes a block [N][3][ncols] with 32-bit offsets, so n_disp * ncols
+ * must stay below 2^32.  nm_pencil_apply, nm_filter_apply, nm_filtered_eig
+ * (block width) and nm_filtered_eig_slices (the sum of the windows' block
+ * widths, which share one block) return NM_EINVAL for wider blocks before
+ * allocating or launching anything.  Host-only; NM_EINVAL if n_disp <= 0. */
+nm_status nm_max_block_columns(int64_t n_disp, int64_t* max_cols);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* nm_last_error(void);

@@ -29,7 +29,7 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_filtered_eig_slices", "nm_project_rotation", "nm_pencil_autotune", "nm_server_create",
             "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
-            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator"]
+            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns"]
 
 
 class NMError(RuntimeError):
@@ -151,6 +151,7 @@ def load_library(path: str | None = None):
         "nm_last_error": ([], C.c_char_p),
         "nm_version": ([], C.c_char_p),
         "nm_set_allocator": ([_ALLOC_FN, _FREE_FN, P], C.c_int32),
+        "nm_max_block_columns": ([C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -196,6 +197,14 @@ def use_torch_allocator():
     device current now."""
     dev = torch.cuda.current_device()
     set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device=dev), torch.cuda.caching_allocator_delete)
+
+
+def max_block_columns(n_disp):
+    """Widest vector block (columns) the kernels accept for n_disp displacement rows."""
+    lib = load_library()
+    out = C.c_int64()
+    _check(lib.nm_max_block_columns(int(n_disp), C.byref(out)))
+    return out.value
 
 
 def filter_coeffs(a, b, lmin, lmax, m):

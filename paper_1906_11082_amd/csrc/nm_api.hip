@@ -95,7 +95,14 @@ nm_status nm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx)
     nm::set_alloc_hooks(h);
   })
 }
-const char* nm_version(void) { return "nmodes 0.1 (gfx950)"; }
+const char* nm_version(void) { return "nmodes 0.2 (gfx950)"; }
+
+nm_status nm_max_block_columns(int64_t n_disp, int64_t* max_cols) {
+  NM_TRY({
+    NM_REQUIRE(max_cols && n_disp > 0, NM_EINVAL, "need n_disp > 0 and an output");
+    *max_cols = nm::max_block_columns(n_disp);
+  })
+}
 
 nm_status nm_assemble(const nm_mesh* mesh, const nm_material* mat, const double omega[3], void* stream,
                       nm_pencil** out) {
@@ -251,6 +258,7 @@ nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const v
                           const nm_apply_opts* opts, void* stream) {
   NM_TRY({
     NM_REQUIRE(p && X && Y && X != Y, NM_EINVAL, "invalid pointers");
+    nm::check_block(3 * p->N, ncols);
     nm::api_apply(p, op, ncols, X, Y, make_cfg(p, opts, (hipStream_t)stream), (hipStream_t)stream);
   })
 }
@@ -287,6 +295,7 @@ nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, doubl
                           void* stream) {
   NM_TRY({
     NM_REQUIRE(p && mu && X && Y && X != Y && m >= 0 && e > 0 && ncols > 0, NM_EINVAL, "invalid filter arguments");
+    nm::check_block(3 * p->N, ncols);
     hipStream_t st = (hipStream_t)stream;
     auto cfg = make_cfg(p, opts, st);
     // vectors cross the ABI in canonical node order; the filter runs in the internal order

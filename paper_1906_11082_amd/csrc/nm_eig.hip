@@ -297,6 +297,13 @@ void spectrum_bounds(const nm_pencil* P, int steps_req, uint64_t seed, hipStream
   *lmin_out = std::min(0.0, th[0]) - std::min(rmin, std::fabs(th[0]) + 1e-12);
 }
 
+// block width: given, else the autotuner's (at most nev / 4, in multiples of 8), else 16
+int solve_block_width(const nm_pencil* P, const nm_eig_opts& o, int nev) {
+  const int bs = o.block > 0 ? o.block
+                             : (P->tuned_block > 0 ? std::min(P->tuned_block, std::max(8, nev / 4 / 8 * 8)) : 16);
+  return (int)std::min<int64_t>(bs, 3 * P->N);
+}
+
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
                   nm_eig_result** out, BatchSeat* seat, rocblas_handle blas) {
   FilterBatcher* fb = seat ? seat->fb : nullptr;
@@ -307,10 +314,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   const int prec = o.precision;
   NM_REQUIRE(prec == 0 || prec == 1, NM_EINVAL, "precision must be 0 or 1");
   if (prec == 1) const_cast<nm_pencil*>(P)->ensure_fp32(st);
-  // block width: given, else the autotuner's (at most nev / 4, in multiples of 8), else 16
-  int bs = o.block > 0 ? o.block
-                       : (P->tuned_block > 0 ? std::min(P->tuned_block, std::max(8, nev / 4 / 8 * 8)) : 16);
-  bs = (int)std::min<int64_t>(bs, n);
+  int bs = solve_block_width(P, o, nev);
+  check_block(n, bs);
   int Kmax = o.max_basis > 0 ? o.max_basis
                             : (int)std::min<int64_t>(n, std::max({6 * nev, nev + 16 * bs, 320}));
   Kmax = std::max(Kmax / bs, 2) * bs;

@@ -292,6 +292,8 @@ struct BatchSeat {
   }
 };
 
+// block width of a solve (options, autotuner, default)
+int solve_block_width(const nm_pencil* P, const nm_eig_opts& o, int nev);
 // seat: batch the filter applications with other solves (null factor not allowed);
 // blas: rocBLAS handle to use (null: the pencil's)
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
@@ -302,6 +304,19 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
                          const nm_eig_opts& o, nm_eig_result** out);
 void project_rotation(const nm_pencil* P, const nm_eig_result* basis, double a, double b,
                       hipStream_t st, nm_rot_result** out);
+
+// Vector-block kernels index a block [N][3][ncols] with 32-bit lane ids and
+// element offsets (row * 3 ncols + entry): a block of one launch must hold
+// fewer than 2^32 elements.  Widest block for n = 3N displacement rows:
+constexpr int64_t BLOCK_ELEMS_MAX = (int64_t)UINT32_MAX;
+inline int64_t max_block_columns(int64_t n_disp) { return n_disp > 0 ? (BLOCK_ELEMS_MAX - 1) / n_disp : 0; }
+// throws NM_EINVAL unless n_disp x ncols fits (checked before any allocation or launch)
+inline void check_block(int64_t n_disp, int64_t ncols) {
+  NM_REQUIRE(ncols >= 1 && ncols <= max_block_columns(n_disp), NM_EINVAL,
+             "vector block of " + std::to_string(ncols) + " columns x " + std::to_string(n_disp) +
+                 " rows exceeds the 2^32 elements a launch indexes (at most " +
+                 std::to_string(max_block_columns(n_disp)) + " columns)");
+}
 
 // launch geometry: grid padded to a multiple of 8 workgroups so that the
 // XCD-aware remap in the kernels is a bijection

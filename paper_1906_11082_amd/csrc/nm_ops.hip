@@ -146,6 +146,7 @@ __device__ __forceinline__ Vx<T, V> row_spmv(const int32_t* cl, const T* vl, int
       a[u] = in ? av : T(0);
     }
     Vx<TX, V> x[U];
+    // c * w + e < rows * w < 2^32 for every block a launch accepts (check_block)
 #pragma unroll
     for (int u = 0; u < U; ++u) x[u] = ldv<TX, V>(X + (size_t)(c[u] * w + e));
 #pragma unroll
@@ -1077,6 +1078,7 @@ void set_mass_passes(nm_pencil* P, ApplyCfg& cfg, int passes, double mtol, int k
 template <class T>
 void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
              hipStream_t st) {
+  check_block(3 * P->N, ncols);
   w.ensure(P, ncols);
   b_apply_impl<T>(P, ncols, X, Y, Update{}, cfg, w, st);
 }
@@ -1087,6 +1089,7 @@ template <class T>
 static void filter_run(const nm_pencil* P, const double* mu, const T* MUd, int m, double c, double e, double l0,
                        double s0, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
                        hipStream_t st) {
+  check_block(3 * P->N, ncols);
   w.ensure(P, ncols);
   const int64_t n = P->N * 3 * ncols;
   if (m == 0 && s0 == 0.0) {
@@ -1349,7 +1352,7 @@ void permute_rows(int64_t rows, int w, const void* src, void* dst, const int32_t
 
 void api_apply(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg,
                hipStream_t st) {
-  NM_REQUIRE(ncols > 0, NM_EINVAL, "ncols must be positive");
+  check_block(3 * P->N, ncols);
   const int eb = cfg.precision == 1 ? 4 : 8;
   const bool in_disp = !(op == NM_OP_KP || op == NM_OP_EG || op == NM_OP_KPINV);
   const bool out_disp = !(op == NM_OP_KP || op == NM_OP_EGT || op == NM_OP_KPINV);
@@ -1372,7 +1375,7 @@ void api_apply(const nm_pencil* P, int op, int ncols, const void* X, void* Y, co
 }
 
 void apply_op(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg, hipStream_t st) {
-  NM_REQUIRE(ncols > 0, NM_EINVAL, "ncols must be positive");
+  check_block(3 * P->N, ncols);
   if (cfg.precision == 1) {
     const_cast<nm_pencil*>(P)->ensure_fp32(st);
     apply_op_t<float>(P, op, ncols, X, Y, cfg, st);

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <thread>
 
 #include "nm_internal.h"
@@ -205,7 +206,12 @@ nm_status nm_server_submit(nm_server* sv, const nm_request* q, int64_t* ticket) 
     const nm_material& mt = q->material;
     NM_REQUIRE(m.xyz && m.tet && m.region && mt.rho && mt.lam && mt.mu && m.n_vert > 0 && m.n_tet > 0, NM_EINVAL,
                "request without mesh or material");
-    Job* j = new Job();
+    {
+      std::lock_guard<std::mutex> lk(sv->mx);
+      NM_REQUIRE(!sv->stopping, NM_EINVAL, "server is shutting down");
+    }
+    std::unique_ptr<Job> jp(new Job());
+    Job* j = jp.get();
     const int64_t V = m.n_vert, T = m.n_tet;
     j->xyz.assign(m.xyz, m.xyz + 3 * V);
     j->tet.assign(m.tet, m.tet + 4 * T);
@@ -239,10 +245,12 @@ nm_status nm_server_submit(nm_server* sv, const nm_request* q, int64_t* ticket) 
     j->opts = q->opts;
     j->rotate = q->rotate;
     j->est = nm::request_bytes(j->mesh, q->nslices, q->nev, q->opts);
-    j->res = (nm_server_result*)std::calloc(1, sizeof(nm_server_result));
-    j->res->est_bytes = j->est;
     std::lock_guard<std::mutex> lk(sv->mx);
     NM_REQUIRE(!sv->stopping, NM_EINVAL, "server is shutting down");
+    j->res = (nm_server_result*)std::calloc(1, sizeof(nm_server_result));
+    NM_REQUIRE(j->res, NM_ENOMEM, "host allocation failed");
+    j->res->est_bytes = j->est;
+    jp.release();  // owned by the server from here on
     j->id = sv->next_id++;
     j->res->t_submit = sv->now();
     sv->jobs[j->id] = j;
@@ -259,10 +267,11 @@ nm_status nm_server_wait(nm_server* sv, int64_t ticket, nm_server_result** out) 
     {
       std::unique_lock<std::mutex> lk(sv->mx);
       auto it = sv->jobs.find(ticket);
-      NM_REQUIRE(it != sv->jobs.end(), NM_EINVAL, "unknown ticket");
+      NM_REQUIRE(it != sv->jobs.end(), NM_EINVAL, "unknown ticket (or already waited for)");
       j = it->second;
-      sv->cv.wait(lk, [&] { return j->done; });
+      // claim the ticket before waiting: a second waiter on it gets NM_EINVAL
       sv->jobs.erase(it);
+      sv->cv.wait(lk, [&] { return j->done; });
     }
     if (j->th.joinable()) j->th.join();
     *out = j->res;

@@ -49,6 +49,7 @@ void FilterBatcher::run_locked() {
       ct += q->bs;
       mmax = std::max(mmax, q->m);
     }
+    check_block(n, ct);
     // per-column series, zero-padded to the largest degree
     std::vector<double> mu((size_t)(mmax + 1) * ct, 0.0);
     int o = 0;
@@ -102,6 +103,12 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
   }
   NM_REQUIRE(o.null_filter != 1, NM_EINVAL, "batched slices do not take the null factor");
   NM_REQUIRE(o.precision == 0 || o.precision == 1, NM_EINVAL, "precision must be 0 or 1");
+  {
+    // the batched filter block concatenates every window's block
+    int64_t width = 0;
+    for (int i = 0; i < S; ++i) width += solve_block_width(P, o, nev[i]);
+    check_block(3 * P->N, width);
+  }
   hipStream_t st = (hipStream_t)o.stream;
   int dev = 0;
   NM_HIP(hipGetDevice(&dev));

@@ -127,3 +127,17 @@ def test_set_allocator_arguments(lib):
         nm.set_allocator(alloc=lambda n: 0)
     nm.set_allocator(None, None)
     assert lib.nm_last_error().decode() == ""
+
+
+def test_block_width_guard(lib):
+    """Vector blocks are indexed with 32-bit offsets: the widest accepted block
+    for n displacement rows keeps n * ncols below 2^32 (the C5-sized body with
+    16 windows of 64 columns would not fit), and the query rejects n <= 0."""
+    import paper_1906_11082_amd as nm
+    for n in (2187, 1_633_791, 5_000_000, 15_000_000):
+        k = nm.max_block_columns(n)
+        assert k >= 1 and n * k < 2 ** 32 and n * (k + 1) >= 2 ** 32 - 1
+    assert nm.max_block_columns(5_000_000) < 16 * 64
+    with pytest.raises(nm.NMError) as e:
+        nm.max_block_columns(0)
+    assert e.value.status == -1
