@@ -1,22 +1,36 @@
 #!/usr/bin/env python3
 """Throughput of the normal-mode eigensolve on one MI355X.
 
-Workload (one "step"): the three-layer planet (solid inner core r < 0.19,
-fluid outer core to 0.55, solid mantle to 1; smooth layered profiles times a
-2 % Gaussian random field in the solids; 384,000 tetrahedra; P2 displacement
-and P1 pressure, 1.63M displacement DOFs), Cowling approximation: assembly of
-the pencil on the device and the polynomial-filtered Lanczos solve for all
-eigenpairs with omega^2 in [1, 60] (nev cap 200), residual tolerance 1e-8.
+Workload: the rotating three-layer planet (solid inner core r < 0.19, fluid
+outer core to 0.55, solid mantle to 1; smooth layered profiles times a 2 %
+Gaussian random field in the solids; 384,000 tetrahedra; P2 displacement and
+P1 pressure, 1.63M displacement DOFs), Cowling approximation, rotation
+Omega = 0.05 along z: all eigenpairs with omega^2 in [1, 60] (nev cap 200,
+residual tolerance 1e-8) by the polynomial-filtered Lanczos solve, then the
+Coriolis term by projection on those pairs.
 
-By default the filter runs in FP64 with each mass solve as two FP32
-Chebyshev-Jacobi passes joined by an FP64 residual correction (--mass-passes 2,
-dtype "f64+f32"); --mass-passes 0 is the all-FP64 solve, --precision fp32 the
-FP32 filter.  Every returned pair's residual is computed in FP64.
+One timed "step" is one application of B = M^{-1} A inside the polynomial
+filter on the solve's full 32-column block: the Cowling operator (A_G with
+the E_G K_p^{-1} E_G^T Schur part), the Chebyshev-Jacobi mass solve and the
+fused three-term filter update.  --warmup untimed and --steps timed steps
+run as one filter application each (degree = that count), bracketed by
+device synchronisations; ms_per_step is the timed one divided by --steps.
 
-Prints one JSON line: eigenpairs/s with residual <= tol over the timed steps,
-the roofline of the dominant kernel (the fused Chebyshev-Jacobi mass-solve
-step inside the filter; mean duration from HIP events recorded by the
-library on the solve's stream) and the CPU oracle's rate on a bounded sample.
+The eigenpair rate comes from full solves run in the same command ("legs"):
+  fp64   the all-FP64 filter (mass solve one FP64 Chebyshev-Jacobi pass);
+  mixed  FP64 filter with every mass solve as two FP32 passes joined by an
+         FP64 residual correction;
+  fp32   FP32 filter (values, vectors, accumulation) with FP64 Lanczos,
+         Rayleigh-Ritz, residuals and a final FP64 refinement.
+The first leg named by --legs is the headline (`value`); the others run while
+the wall-clock budget allows (a leg that would not fit is reported null with
+the reason).  Every returned pair's residual is computed in FP64 against the
+FP64 pencil; value = pairs with residual <= tol / (solve + projection) seconds,
+with the pencil resident in HBM (assembly timed separately).
+
+Also printed: the roofline of the dominant kernel (a middle Chebyshev-Jacobi
+step of the mass solve; mean duration from HIP events the library records on
+the solve's stream) and the CPU oracle's rate on a bounded sample.
 """
 import argparse
 import json
@@ -29,85 +43,133 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "eigenpairs/s at resid≤1e-8, FP32-filter vs FP64; SpMM HBM GB/s; p99 latency"
+T0 = time.perf_counter()
+
+LEGS = {
+    "fp64": dict(precision=0, mass_passes=0, dtype="f64"),
+    "mixed": dict(precision=0, mass_passes=2, dtype="f64+f32"),
+    "fp32": dict(precision=1, mass_passes=0, dtype="f32+f64"),
+}
 
 
-def cpu_baseline(gpu_result, gpu_nnzb, args):
-    """The oracle (scipy CSR products, Chebyshev-Jacobi mass solve) timed on
-    column B-applications of the same planet family at n_half = 8, scaled by
-    the node-graph size to the full workload and multiplied by the GPU run's
-    B-application count (extrapolated; the oracle's Lanczos and
-    Rayleigh-Ritz work is not counted, which favours the oracle)."""
+def log(msg):
+    print("[bench %6.1fs] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
+
+
+_ORACLE = {}
+
+
+def _oracle_worker(args):
+    """Column B-applications of the oracle on `ncols` columns for about `seconds`
+    (one single-threaded pool process; the oracle pencil is built on first use)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
-    import planetgen as pg
-    from oracle.assemble import Pencil
-    from oracle import solve as S
-    nh = args.cpu_n_half
-    planet = pg.three_layer_planet(n_half=nh)
+    nh, tol, ncols, seconds, seed = args
     with threadpool_limits(limits=1):
-        P = Pencil(planet)
-        op = S.CowlingOperator(P, minv_tol=args.minv_tol if args.minv_tol > 0 else 0.3 * args.tol, kp_tol=1e-13)
-        rng = np.random.default_rng(0)
-        X = rng.standard_normal((P.n, 4))
+        if nh not in _ORACLE:
+            import planetgen as pg
+            from oracle.assemble import Pencil
+            from oracle import solve as S
+            t = time.perf_counter()
+            P = Pencil(pg.three_layer_planet(n_half=nh))
+            ptr, _ = P.nb.node_graph()
+            _ORACLE[nh] = (S.CowlingOperator(P, minv_tol=0.3 * tol, kp_tol=1e-13), int(ptr[-1]),
+                           time.perf_counter() - t)
+        op, nnzb, t_asm = _ORACLE[nh]
+        X = np.random.default_rng(seed).standard_normal((op.n, ncols))
         op.B(X)
-        reps = 0
-        t0 = time.perf_counter()
+        reps, t0 = 0, time.perf_counter()
         while True:
             op.B(X)
             reps += 1
-            if time.perf_counter() - t0 > args.cpu_seconds:
+            if time.perf_counter() - t0 > seconds:
                 break
         dt = time.perf_counter() - t0
-    per_col = dt / (reps * X.shape[1])
-    ptr, _ = P.nb.node_graph()
-    scale = gpu_nnzb / float(ptr[-1])
-    t_solve = per_col * scale * gpu_result.stats["bapps"]
-    pairs = int((gpu_result.resid <= args.tol).sum())
+    return dict(cols=reps * ncols, seconds=dt, pid=os.getpid(), n=op.n, nnzb=nnzb, kM=op.kM, kP=op.kP,
+                asm=t_asm)
+
+
+def cpu_baseline(pool, cores, gpu_stats, pairs, gpu_nnzb, args):
+    """The oracle (scipy CSR products and its own Chebyshev-Jacobi mass solve,
+    the same Cowling operator and mass-solve bound as the GPU leg) timed on
+    column B-applications of the same planet generator at n_half = cpu_n_half,
+    once on one core and once on `cores` cores (one single-threaded process
+    per core, 4 columns each).  Scaled to the workload by node-graph size and
+    multiplied by the GPU leg's column B-application count: an extrapolated
+    oracle solve time (its Lanczos and Rayleigh-Ritz are not counted, which
+    favours the oracle)."""
+    one = pool.apply(_oracle_worker, ((args.cpu_n_half, args.tol, 4, args.cpu_seconds, 0),))
+    outs = pool.map(_oracle_worker, [(args.cpu_n_half, args.tol, 4, args.cpu_seconds, 1 + i)
+                                     for i in range(cores)], chunksize=1)
+    used = len({o["pid"] for o in outs})  # processes that ran concurrently
+    rate_all = sum(o["cols"] / o["seconds"] for o in outs) * used / len(outs)
+    per_col_1 = one["seconds"] / one["cols"]
+    per_col_all = 1.0 / rate_all
+    scale = gpu_nnzb / float(one["nnzb"])
+    bapps = gpu_stats["bapps"] + gpu_stats["refine_bapps"]
+    t_1 = per_col_1 * scale * bapps
+    t_all = per_col_all * scale * bapps
     return {
-        "value": pairs / t_solve if t_solve > 0 else None,
+        "value": pairs / t_all if t_all > 0 else None,
         "unit": "eigenpairs/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": ("%d x 4-column B-applications (A + Schur + %d-step Chebyshev-Jacobi M^-1) of the oracle on the "
-                   "same planet generator at n_half=%d (%d DOF, %.1f s), scaled by node-graph size x%.1f to this "
-                   "workload and by its %d column B-applications; single-threaded scipy CSR"
-                   % (reps, op.kM, nh, P.n, dt, scale, gpu_result.stats["bapps"])),
-        "seconds_per_column_bapp_full_size": per_col * scale,
+        "sample": ("column B-applications (A_G + E_G K_p^-1 E_G^T with a %d-step K_p solve, then the %d-step "
+                   "Chebyshev-Jacobi M solve) of the oracle on the same planet generator at n_half=%d (%d DOF, "
+                   "nnzb %d), ~%.0f s on 1 core and ~%.0f s on %d cores (one single-threaded process each, 4 "
+                   "columns); per-column time scaled by node-graph size x%.2f to this workload and multiplied "
+                   "by the headline solve's %d column B-applications (extrapolated; Lanczos and Rayleigh-Ritz "
+                   "not counted)" % (one["kP"], one["kM"], args.cpu_n_half, one["n"], one["nnzb"],
+                                    one["seconds"], max(o["seconds"] for o in outs), used, scale, bapps)),
+        "value_1core": pairs / t_1 if t_1 > 0 else None,
+        "seconds_per_column_bapp_full_size_1core": per_col_1 * scale,
+        "seconds_per_column_bapp_full_size_all_cores": per_col_all * scale,
+        "extrapolated_solve_seconds_1core": t_1,
+        "extrapolated_solve_seconds_all_cores": t_all,
+        "oracle_assembly_seconds": one["asm"],
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--steps", type=int, default=20, help="timed B-applications (one filter application)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed B-applications before them")
+    ap.add_argument("--legs", default="mixed,fp64,fp32",
+                    help="comma-separated solve legs (fp64, mixed, fp32); the first is the headline")
+    ap.add_argument("--budget-s", type=float, default=470.0,
+                    help="wall-clock budget from process start: later legs that would not fit are skipped")
     ap.add_argument("--n-half", type=int, default=20)
+    ap.add_argument("--omega", type=float, default=0.05, help="rotation rate about z (0: no projection)")
     ap.add_argument("--a", type=float, default=1.0)
     ap.add_argument("--b", type=float, default=60.0)
     ap.add_argument("--nev", type=int, default=200)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--guard", type=float, default=1.0)
     ap.add_argument("--block", type=int, default=32)
-    ap.add_argument("--minv-tol", type=float, default=0.0, help="mass-solve bound (0: library default, 0.3 tol)")
     ap.add_argument("--max-basis", type=int, default=1400)
-    ap.add_argument("--mass-passes", type=int, default=2,
-                    help="FP64 filter with the mass solve in this many FP32 passes with FP64 residual corrections "
-                         "(0: one FP64 pass; ignored with --precision fp32)")
     ap.add_argument("--cpu-n-half", type=int, default=8)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--cpu-cores", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default="", help="PMC traffic summary of the hot kernel (default: "
-                    "profiles/<kernel>_c2_<precision>_b<block>_traffic.json)")
-    ap.add_argument("--quiet", action="store_true", help="no per-block progress lines on stderr")
-    ap.add_argument("--omega", type=float, default=0.0,
-                    help="rotation rate about z: the step also projects the Coriolis term over the window's pairs")
+    ap.add_argument("--quiet", action="store_true", help="no per-block solver lines on stderr")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: the library runs on one GPU only (no multi-GPU path); --gpus %d is not supported"
-              % args.gpus, file=sys.stderr)
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU sharding is "
+              "described in the design notes, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    for x in legs:
+        if x not in LEGS:
+            ap.error("unknown leg %r" % x)
+    pool, cores = None, 0
+    if not args.no_cpu_baseline:
+        # the oracle's processes are forked before anything touches the GPU
+        import multiprocessing as mp
+        cores = max(1, min(args.cpu_cores, os.cpu_count() or 1))
+        pool = mp.get_context("fork").Pool(cores)
 
+    import numpy as np
     import torch
     import planetgen as pg
     import paper_1906_11082_amd as nm
@@ -115,88 +177,126 @@ def main():
     nm.load_library()
     torch.cuda.set_device(0)
     planet = pg.three_layer_planet(n_half=args.n_half, omega=(0.0, 0.0, args.omega))
-    prec = 1 if args.precision == "fp32" else 0
-    if prec:
-        args.mass_passes = 0
+    log("planet: %d tets" % len(planet["tet"]))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P = nm.Pencil(planet)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t
+    log("assembly %.2f s: n %d, n_p %d, nnzb %d" % (t_asm, P.n, P.n_p, P.info["nnzb"]))
 
-    rot = {}
+    # ---- timed steps: B-applications of the headline leg's filter on the full block
+    head = LEGS[legs[0]]
+    lo, hi = P.spectrum_bounds(60, 0x5BD1E995)
+    lmin, lmax = lo - 1e-3 * (args.b - args.a), hi
+    c, e = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    X = torch.randn(P.n, args.block, dtype=torch.float32 if head["precision"] else torch.float64, device="cuda")
+    kw = dict(minv_tol=0.3 * args.tol if not head["precision"] else 1e-7,
+              kp_tol=1e-13 if not head["precision"] else 1e-7,
+              precision=head["precision"], mass_passes=head["mass_passes"])
+    if args.warmup > 0:
+        P.filter_apply(nm.filter_coeffs(args.a, args.b, lmin, lmax, args.warmup), c, e, X, **kw)
+    mu = nm.filter_coeffs(args.a, args.b, lmin, lmax, max(args.steps, 1))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P.filter_apply(mu, c, e, X, **kw)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t
+    ms_per_step = t_steps / max(args.steps, 1) * 1e3
+    log("%d B-applications (block %d, %s): %.2f ms each" % (args.steps, args.block, legs[0], ms_per_step))
 
-    def step():
-        P = nm.Pencil(planet)
+    # ---- full solves
+    results = {}
+    first_seconds = None
+    for i, name in enumerate(legs):
+        L = LEGS[name]
+        elapsed = time.perf_counter() - T0
+        if i > 0:
+            # a later leg is estimated from the headline solve's length (the FP32 filter with its
+            # refinement and the all-FP64 solve have measured up to ~1.6x the mixed one)
+            est = 1.7 * first_seconds
+            if elapsed + est > args.budget_s:
+                results[name] = dict(value=None, reason="not run: the estimated %.0f s would exceed the %.0f s "
+                                     "budget (%.0f s elapsed)" % (est, args.budget_s, elapsed))
+                log("leg %s skipped (estimate %.0f s)" % (name, est))
+                continue
+        log("leg %s: solve" % name)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
         r = P.filtered_eig(args.a, args.b, args.nev, args.tol, block=args.block, guard=args.guard,
-                           precision=prec, minv_tol=args.minv_tol, max_basis=args.max_basis,
-                           verbose=0 if args.quiet else 1, allow_partial=True, mass_passes=args.mass_passes)
-        if args.omega != 0.0:
-            t = time.perf_counter()
+                           precision=L["precision"], max_basis=args.max_basis, lmin=lmin, lmax=lmax,
+                           verbose=0 if args.quiet else 1, allow_partial=True, mass_passes=L["mass_passes"])
+        rot = None
+        if args.omega != 0.0 and r.count:
             rr = P.project_rotation(r, args.a, args.b)
-            rot.update(count=rr.count, seconds=time.perf_counter() - t,
-                       omega_min=float(rr.omega.min()) if rr.count else None,
-                       omega_max=float(rr.omega.max()) if rr.count else None)
-        return P, r
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = []
-    for _ in range(args.steps):
-        P, r = step()
-        res.append(r)
-        print("[bench] step done: %d pairs, %.1f s" % (r.count, r.stats["seconds"]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    T = t1 - t0
-    pairs = sum(int((r.resid <= args.tol).sum()) for r in res)
-    last = res[-1]
-    st = last.stats
+            rot = dict(count=rr.count, omega_min=float(rr.omega.min()) if rr.count else None,
+                       omega_max=float(rr.omega.max()) if rr.count else None, seconds=rr.seconds)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t
+        if first_seconds is None:
+            first_seconds = secs
+        st = r.stats
+        pairs = int((r.resid <= args.tol).sum())
+        results[name] = dict(
+            value=pairs / secs, unit="eigenpairs/s", dtype=L["dtype"], seconds=secs, pairs=pairs, count=r.count,
+            resid_max=float(r.resid.max()) if r.count else None, partial=bool(r.partial),
+            filter_degree=st["degree"], kM=st["kM"], mass_passes=st["mass_passes"],
+            mass_pass_steps=st["mass_pass_steps"], block=st["block"], basis=st["basis"],
+            column_bapps=st["bapps"], filter_seconds=st["filter_seconds"], refine_passes=st["refine_passes"],
+            refine_degree=st["refine_degree"], refine_seconds=st["refine_seconds"],
+            refine_column_bapps=st["refine_bapps"], rotating_modes=rot,
+            hot_kernel_ms=st["hot_ms"], hot_kernel_bytes=st["hot_bytes"], hot_samples=st["hot_samples"],
+            _lam=r.lam, _stats=st)
+        log("leg %s: %d pairs <= tol in %.1f s (%.3f eigenpairs/s), resid max %.2e"
+            % (name, pairs, secs, pairs / secs, results[name]["resid_max"] or 0.0))
+        if i == 0 and not args.no_cpu_baseline:
+            log("cpu baseline")
+            cpu = cpu_baseline(pool, cores, st, pairs, P.info["nnzb"], args)
+            pool.close()
+            log("cpu baseline done: %.3g eigenpairs/s on %d cores" % (cpu["value"], cpu["cores"]))
+    # accuracy of each leg against the FP64 leg (eigenvalues of matched pairs)
+    ref = results.get("fp64", {}).get("_lam")
+    for name, R in results.items():
+        lam = R.pop("_lam", None)
+        if name != legs[0]:
+            R.pop("_stats", None)
+        if ref is not None and lam is not None and name != "fp64":
+            k = min(len(ref), len(lam))
+            R["max_rel_eig_diff_vs_fp64"] = float(np.max(np.abs(lam[:k] - ref[:k]) / np.abs(ref[:k]))) if k else None
+    H = results[legs[0]]
+    st = H.pop("_stats")
     hot_gbs = st["hot_bytes"] / (st["hot_ms"] * 1e-3) / 1e9 if st["hot_ms"] > 0 else None
-    traffic = None
-    # the sampled kernel: a middle step of the FP64 mass solve, or of an FP32 pass
-    hot_prec = "fp32" if prec else ("mixed" if args.mass_passes else "fp64")
-    hot = "k_cj_group" if st["block"] >= 32 else "k_cj_step"
-    if not args.traffic_json:
-        args.traffic_json = os.path.join(ROOT, "profiles", "%s_c2_%s_b%d_traffic.json" % (hot, hot_prec,
-                                                                                           st["block"]))
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        if tj.get("precision") == hot_prec and tj.get("block") == args.block and \
-                tj.get("n_half") == args.n_half:
-            traffic = tj.get("hbm_bytes_per_launch")
     out = {
         "metric": METRIC,
-        "value": pairs / T,
+        "value": H["value"],
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": T / args.steps * 1e3,
+        "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec else ("f64+f32" if args.mass_passes else "f64"),
+        "dtype": H["dtype"],
         "data": "synthetic",
         "config": {
-            "workload": "three-layer planet, %d tets, P2/P1, Cowling, omega^2 in [%g, %g], nev<=%d, tol %g"
-                        % (len(planet["tet"]), args.a, args.b, args.nev, args.tol),
-            "n_disp": P.info["n_disp"], "n_pres": P.info["n_pres"], "nnzb": P.info["nnzb"],
-            "filter_degree": st["degree"], "kM": st["kM"], "block": st["block"], "basis": st["basis"],
-            "mass_passes": st["mass_passes"], "mass_pass_steps": st["mass_pass_steps"],
-            "column_bapps": st["bapps"], "pairs": last.count, "resid_max": float(last.resid.max()) if last.count else None,
-            "lmax": st["lmax"], "solve_seconds": st["seconds"], "filter_seconds": st["filter_seconds"],
-            "partial": bool(last.partial),
-            "refine_passes": st["refine_passes"], "refine_degree": st["refine_degree"],
-            "refine_seconds": st["refine_seconds"], "refine_column_bapps": st["refine_bapps"],
-            "omega_z": args.omega, "rotating_modes": rot or None,
+            "workload": "rotating three-layer planet, %d tets, P2/P1, Cowling, Omega=%g z, omega^2 in [%g, %g], "
+                        "nev<=%d, tol %g" % (len(planet["tet"]), args.omega, args.a, args.b, args.nev, args.tol),
+            "step": "one B = M^-1 A application inside the filter on the %d-column block (%s leg)"
+                    % (args.block, legs[0]),
+            "headline_leg": legs[0],
+            "n_disp": P.n, "n_pres": P.n_p, "nnzb": P.info["nnzb"], "assembly_seconds": t_asm,
+            "lmin": lmin, "lmax": lmax,
         },
+        "legs": results,
         "roofline": {
             "bound": "hbm",
             "achieved": hot_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": hot_gbs / HBM_PEAK_GBS if hot_gbs else None,
-            "traffic": traffic,
-            "kernel": hot + " (fused Chebyshev-Jacobi step of the mass solve)",
+            "traffic": None,
+            "kernel": "middle Chebyshev-Jacobi step of the mass solve (%s leg)" % legs[0],
             "bytes_per_launch": st["hot_bytes"],
             "mean_launch_ms": st["hot_ms"],
             "sampled_launches": st["hot_samples"],
@@ -204,7 +304,7 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(last, P.info["nnzb"], args)
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

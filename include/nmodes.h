@@ -182,6 +182,8 @@ typedef struct {
   int64_t refine_bapps;
   /* M solve inside the filter: FP32 passes (0: one FP64 pass of kM steps) and steps per pass */
   int32_t mass_passes, mass_pass_steps;
+  /* kernel of the middle mass-solve steps: 0 per-row, 1 row groups, 2 LDS tiles */
+  int32_t hot_kernel;
 } nm_eig_result;
 
 typedef struct {
@@ -254,6 +256,25 @@ nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, doubl
  * in the M-inner product with the random start vector of `seed`. */
 nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, void* stream, double* lmin,
                              double* lmax);
+
+/* Density of states of B = M^{-1} A by the kernel polynomial method (the
+ * spectrum slicing of Sec. 6.1 follows EVSL, which places slices by such an
+ * estimate): tau[k] = (1/nvec) sum_v z_v^T T_k((B - c)/e) z_v, k = 0..m,
+ * c -+ e = [lmin, lmax], by the filter's three-term recurrence on the nvec
+ * columns of Z (device, [n][nvec], canonical order, caller-drawn; with
+ * E[z z^T] = I each tau[k] estimates tr T_k).  FP64 operators (opts as for
+ * nm_pencil_apply; precision must be 0).  tau: host [m + 1]. */
+nm_status nm_spectrum_dos(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec, const double* Z,
+                          const nm_apply_opts* opts, void* stream, double* tau);
+/* Estimated number of eigenvalues in [a, b] from traces tau[0..m]: the
+ * Jackson-damped Chebyshev series of the indicator (nm_filter_coeffs) dotted
+ * with tau.  Host only. */
+nm_status nm_dos_count(const double* tau, int32_t m, double lmin, double lmax, double a, double b, double* count);
+/* Ends edges[0..nslices] (edges[0] = a, edges[nslices] = b) of nslices
+ * windows of [a, b] with equal estimated counts (bisection on the
+ * cumulative count).  Host only. */
+nm_status nm_dos_slices(const double* tau, int32_t m, double lmin, double lmax, double a, double b, int32_t nslices,
+                        double* edges);
 
 /* Eigenpairs of the Cowling pencil with a <= omega^2 <= b: the min(nev,
  * count) smallest, by polynomial-filtered block Lanczos in the M-inner

@@ -16,6 +16,8 @@ computing seismic normal modes in rotating planets", arXiv 1906.11082):
                   (Sec. 6.1 and the polynomial-filtering remark of Sec. 2.5).
 * ``rotation`` -- the projected Hermitian problem for the Coriolis QEP
                   (Sec. 7, eqs. "simplequad", "linearpb", "sublinear0").
+* ``dos``      -- density of states by the kernel polynomial method and
+                  equal-count spectrum slices (Sec. 6.1, spectrum slicing).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
 of ``bench.py`` may import this package.  It shares no code with the GPU

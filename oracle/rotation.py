@@ -61,3 +61,36 @@ def first_order_splitting(U, Rop):
     S = U.T @ Rop(U)
     S = 0.5 * (S - S.T)
     return np.linalg.eigvalsh(1j * S)
+
+
+def qep_exact(A, M, R, a, b):
+    """The rotating modes of the full discrete QEP (eq. "simplequad"),
+    omega^2 M u - 2 i omega R u - A u = 0, with omega > 0 and omega^2 in
+    [a, b]: eigenvalues of the first companion form
+    [[0, I], [M^{-1} A, 2 i M^{-1} R]] acting on [u; omega u] (dense, numpy),
+    ascending, with their modes normalised by eq. "orthonormalcond"
+    (u^H M u - (i / omega) u^H R u = 1).  Unlike the projection, nothing is
+    left out: rigid motions and the fluid null space of A couple too."""
+    n = A.shape[0]
+    Mi = np.linalg.inv(M)
+    L = np.block([[np.zeros((n, n)), np.eye(n)], [Mi @ A, 2j * (Mi @ R)]])
+    w, Z = np.linalg.eig(L)
+    scale = np.abs(w).max()
+    sel = (np.abs(w.imag) <= 1e-8 * scale) & (w.real > 0)
+    w, Z = w[sel].real, Z[:, sel]
+    keep = (w * w >= a) & (w * w <= b)
+    w, U = w[keep], Z[:n, keep]
+    o = np.argsort(w)
+    w, U = w[o], U[:, o]
+    nrm = np.real(np.einsum("ik,ik->k", U.conj(), M @ U) - 1j / w * np.einsum("ik,ik->k", U.conj(), R @ U))
+    U = U / np.sqrt(nrm)[None, :]
+    idx = np.argmax(np.abs(U), axis=0)
+    ph = U[idx, np.arange(U.shape[1])]
+    U = U * (np.abs(ph) / ph)[None, :]
+    return w, U
+
+
+def qep_residual(A, M, R, omega, U):
+    """|| omega^2 M u - 2 i omega R u - A u || / (omega^2 || M u ||) per mode."""
+    Rr = (M @ U) * omega ** 2 - 2j * (R @ U) * omega - A @ U
+    return np.linalg.norm(Rr, axis=0) / (omega ** 2 * np.linalg.norm(M @ U, axis=0))

@@ -211,6 +211,51 @@ def dense_window(A, M, a, b):
     return w, X
 
 
+def cowling_window(pencil, a, b, pieces=None, k0=48, tol=1e-13, permc_spec="MMD_AT_PLUS_A"):
+    """All eigenpairs of the Cowling pencil (eq. "cowling": A_G + E_G K_p^{-1}
+    E_G^T with the exact Schur complement) with a <= lambda <= b, a > 0,
+    ascending, M-orthonormal: shift-invert Lanczos (ARPACK through scipy) at
+    the midpoint of each of `pieces` equal sub-intervals of [a, b], the
+    shifted solve done by one sparse LU of the saddle-point system
+    [[A_G - s M, E_G], [E_G^T, -K_p]].  Shift-invert returns the k
+    eigenvalues nearest the shift; k grows until the farthest of them lies
+    outside the sub-interval, so every eigenvalue inside it is found (the
+    exactly degenerate fluid null space at 0 lies farther from every shift
+    than the sub-interval's ends)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n, n_p = pencil.n, pencil.n_p
+    kp = pencil.kp_direct() if n_p else None
+    Aop = spla.LinearOperator((n, n), matvec=lambda x: pencil.cowling_apply(x, kp), dtype=float)
+    pieces = pieces or max(1, int(math.ceil((b - a) / 12.0)))
+    edges = np.linspace(a, b, pieces + 1)
+    lams, vecs = [], []
+    for i in range(pieces):
+        lo, hi = edges[i], edges[i + 1]
+        s, r = 0.5 * (lo + hi), 0.5 * (hi - lo)
+        if n_p:
+            K = sp.bmat([[pencil.AG - s * pencil.M, pencil.EG], [pencil.EG.T, -pencil.Kp]], format="csc")
+        else:
+            K = (pencil.AG - s * pencil.M).tocsc()
+        lu = spla.splu(K, permc_spec=permc_spec)
+        Sop = spla.LinearOperator((n, n), dtype=float,
+                                  matvec=lambda f: lu.solve(np.concatenate([f, np.zeros(n_p)]))[:n])
+        k = k0
+        while True:
+            k = min(k, n - 2)
+            w, V = spla.eigsh(Aop, k=k, M=pencil.M, sigma=s, OPinv=Sop, which="LM", tol=tol)
+            if np.abs(w - s).max() > r * (1 + 1e-9) or k >= n - 2:
+                break
+            k *= 2
+        keep = (w >= lo) & ((w < hi) if i + 1 < pieces else (w <= hi))
+        lams.append(w[keep])
+        vecs.append(V[:, keep])
+    w = np.concatenate(lams)
+    X = np.concatenate(vecs, axis=1)
+    o = np.argsort(w)
+    return w[o], X[:, o]
+
+
 def inertia_count(A, M, sigma):
     """Number of eigenvalues of (A, M) below sigma (Sylvester's law of
     inertia on the dense LDL^T factorisation of A - sigma M)."""

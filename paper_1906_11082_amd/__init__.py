@@ -29,7 +29,8 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_filtered_eig_slices", "nm_project_rotation", "nm_pencil_autotune", "nm_server_create",
             "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
-            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns"]
+            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns",
+            "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices"]
 
 
 class NMError(RuntimeError):
@@ -75,7 +76,7 @@ class _EigResult(C.Structure):
                 ("filter_seconds", C.c_double), ("hot_launches", C.c_int64), ("hot_samples", C.c_int64),
                 ("hot_ms", C.c_double), ("hot_bytes", C.c_double), ("refine_passes", C.c_int32),
                 ("refine_degree", C.c_int32), ("refine_seconds", C.c_double), ("refine_bapps", C.c_int64),
-                ("mass_passes", C.c_int32), ("mass_pass_steps", C.c_int32)]
+                ("mass_passes", C.c_int32), ("mass_pass_steps", C.c_int32), ("hot_kernel", C.c_int32)]
 
 
 class _RotResult(C.Structure):
@@ -152,6 +153,10 @@ def load_library(path: str | None = None):
         "nm_version": ([], C.c_char_p),
         "nm_set_allocator": ([_ALLOC_FN, _FREE_FN, P], C.c_int32),
         "nm_max_block_columns": ([C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
+        "nm_spectrum_dos": ([P, C.c_double, C.c_double, C.c_int32, C.c_int32, P, C.POINTER(_ApplyOpts), P, P],
+                            C.c_int32),
+        "nm_dos_count": ([P, C.c_int32] + [C.c_double] * 4 + [C.POINTER(C.c_double)], C.c_int32),
+        "nm_dos_slices": ([P, C.c_int32] + [C.c_double] * 4 + [C.c_int32, P], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -207,6 +212,24 @@ def max_block_columns(n_disp):
     return out.value
 
 
+def dos_count(tau, lmin, lmax, a, b):
+    """Estimated eigenvalue count in [a, b] from density-of-states traces (nm_dos_count)."""
+    lib = load_library()
+    tau = np.ascontiguousarray(tau, np.float64)
+    out = C.c_double()
+    _check(lib.nm_dos_count(_ptr(tau), len(tau) - 1, lmin, lmax, a, b, C.byref(out)))
+    return out.value
+
+
+def dos_slices(tau, lmin, lmax, a, b, nslices):
+    """Ends of nslices equal-count windows of [a, b] (nm_dos_slices)."""
+    lib = load_library()
+    tau = np.ascontiguousarray(tau, np.float64)
+    edges = np.zeros(nslices + 1)
+    _check(lib.nm_dos_slices(_ptr(tau), len(tau) - 1, lmin, lmax, a, b, int(nslices), _ptr(edges)))
+    return edges
+
+
 def filter_coeffs(a, b, lmin, lmax, m):
     lib = load_library()
     mu = np.zeros(m + 1)
@@ -237,7 +260,8 @@ class EigResult:
                           hot_samples=r.hot_samples, hot_ms=r.hot_ms, hot_bytes=r.hot_bytes,
                           refine_passes=r.refine_passes, refine_degree=r.refine_degree,
                           refine_seconds=r.refine_seconds, refine_bapps=r.refine_bapps,
-                          mass_passes=r.mass_passes, mass_pass_steps=r.mass_pass_steps)
+                          mass_passes=r.mass_passes, mass_pass_steps=r.mass_pass_steps,
+                          hot_kernel=("per-row", "row-group", "tile")[r.hot_kernel])
         self._ptr = ptr
         self.n = r.n
         self.X = None
@@ -350,6 +374,16 @@ class Pencil:
         _check(_lib.nm_filter_apply(self._h, _ptr(mu), len(mu) - 1, c, e, null_shift, null_scale, X.shape[1],
                                     _ptr(X), _ptr(Y), C.byref(o), _stream()))
         return Y
+
+    def spectrum_dos(self, lmin, lmax, m, Z, **kw):
+        """Density-of-states traces tau[0..m] from the columns of the device
+        block Z [n, nvec] (float64, canonical order; nm_spectrum_dos)."""
+        Z = Z.contiguous()
+        tau = np.zeros(m + 1)
+        o = self._opts(**kw)
+        _check(_lib.nm_spectrum_dos(self._h, lmin, lmax, int(m), Z.shape[1], _ptr(Z), C.byref(o), _stream(),
+                                    _ptr(tau)))
+        return tau
 
     def spectrum_bounds(self, steps=60, seed=1):
         lo, hi = C.c_double(), C.c_double()

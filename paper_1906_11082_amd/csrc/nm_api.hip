@@ -319,6 +319,60 @@ nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, doubl
   })
 }
 
+nm_status nm_spectrum_dos(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec, const double* Z,
+                          const nm_apply_opts* opts, void* stream, double* tau) {
+  NM_TRY({
+    NM_REQUIRE(p && Z && tau && m >= 0 && nvec >= 1 && lmax > lmin, NM_EINVAL, "invalid density-of-states arguments");
+    nm::check_block(3 * p->N, nvec);
+    hipStream_t st = (hipStream_t)stream;
+    auto cfg = make_cfg(p, opts, st);
+    NM_REQUIRE(cfg.precision == 0, NM_EINVAL, "the density of states runs in FP64 (precision 0)");
+    const int64_t w = 3 * (int64_t)nvec;
+    nm::DBuf<double> zi((size_t)p->N * w);
+    nm::permute_rows(p->N, (int)w, Z, zi.p, p->iperm.p, 8, st);
+    nm::dos_traces(p, lmin, lmax, m, nvec, zi.p, cfg, st, tau);
+    NM_HIP(hipGetLastError());
+  })
+}
+
+nm_status nm_dos_count(const double* tau, int32_t m, double lmin, double lmax, double a, double b, double* count) {
+  NM_TRY({
+    NM_REQUIRE(tau && count && m >= 0 && lmax > lmin && b > a, NM_EINVAL, "invalid count arguments");
+    std::vector<double> mu(m + 1);
+    nm::jackson_chebyshev(a, b, lmin, lmax, m, mu.data());
+    double s = 0;
+    for (int k = 0; k <= m; ++k) s += mu[k] * tau[k];
+    *count = s;
+  })
+}
+
+nm_status nm_dos_slices(const double* tau, int32_t m, double lmin, double lmax, double a, double b, int32_t nslices,
+                        double* edges) {
+  NM_TRY({
+    NM_REQUIRE(tau && edges && m >= 0 && lmax > lmin && b > a && nslices >= 1, NM_EINVAL, "invalid slice arguments");
+    std::vector<double> mu(m + 1);
+    auto count = [&](double x) {
+      nm::jackson_chebyshev(a, x, lmin, lmax, m, mu.data());
+      double s = 0;
+      for (int k = 0; k <= m; ++k) s += mu[k] * tau[k];
+      return s;
+    };
+    const double total = count(b);
+    edges[0] = a;
+    for (int i = 1; i < nslices; ++i) {
+      const double target = total * i / nslices;
+      double lo = edges[i - 1], hi = b;
+      for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count(mid) < target) lo = mid;
+        else hi = mid;
+      }
+      edges[i] = 0.5 * (lo + hi);
+    }
+    edges[nslices] = b;
+  })
+}
+
 nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, void* stream, double* lmin,
                              double* lmax) {
   NM_TRY({

@@ -814,6 +814,7 @@ void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStre
                        P->mdinv.p);
   }
   build_row_groups(P, st);
+  build_tiles(P, st);
   Ke.release();
   Kf.release();
 

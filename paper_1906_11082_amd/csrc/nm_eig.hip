@@ -1043,6 +1043,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   }
   r->mass_passes = cfg.mixP;
   r->mass_pass_steps = cfg.mixP ? cfg.mixK : cfg.kM;
+  r->hot_kernel = mass_kernel_kind(P, bs, prec == 1 || cfg.mixP > 0);
   r->refine_passes = refine_passes;
   r->refine_degree = kq;
   r->refine_seconds = refine_seconds;

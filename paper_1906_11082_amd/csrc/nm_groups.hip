@@ -157,4 +157,59 @@ void build_row_groups(nm_pencil* P, hipStream_t st) {
   P->grp_coef = std::move(coef);
 }
 
+// LDS tiles for the tiled mass-solve kernel: tiles of TR consecutive rows of
+// the Morton order, the sorted union of their columns (each gathered once
+// per tile into LDS) and the union position of every nonzero.  TR = rows, or
+// (rows 0) NM_TILE_ROWS (default 32); with rows 0 the tiles are built only
+// when NM_TILES=1.
+void build_tiles(nm_pencil* P, hipStream_t st, int rows) {
+  P->tile_rows = 0;
+  P->tile_umax = P->tile_emax = 0;
+  if (rows <= 0) {
+    // off by default: on the P2 planets the 4-row group kernel is faster (the
+    // LDS reads of random union chunks conflict); the autotuner times both
+    const char* env = getenv("NM_TILES");
+    P->tiled = env ? atoi(env) : 0;
+    if (P->tiled <= 0) {
+      P->tiled = 0;
+      return;
+    }
+  } else {
+    P->tiled = 1;
+  }
+  const char* renv = getenv("NM_TILE_ROWS");
+  const int TR = rows > 0 ? rows : (renv ? atoi(renv) : 32);
+  NM_REQUIRE(TR >= 4 && TR <= 256, NM_EINVAL, "NM_TILE_ROWS must be in [4, 256]");
+  const int64_t N = P->N;
+  const int64_t nt = (N + TR - 1) / TR;
+  DBuf<int32_t> cnt(nt);
+  hipLaunchKernelGGL(k_group_union, dim3((unsigned)nt), dim3(256), 0, st, N, TR, P->row_ptr.p, P->col.p, 0, cnt.p,
+                     nullptr, nullptr, nullptr);
+  std::vector<int32_t> h(nt), rp(N + 1);
+  NM_HIP(hipMemcpyAsync(h.data(), cnt.p, 4 * nt, hipMemcpyDeviceToHost, st));
+  NM_HIP(hipMemcpyAsync(rp.data(), P->row_ptr.p, 4 * (N + 1), hipMemcpyDeviceToHost, st));
+  NM_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> ptr(nt + 1, 0);
+  int umax = 0, emax = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    if (h[t] < 0) return;  // a tile's entries do not fit the union sort: no tiles
+    ptr[t + 1] = ptr[t] + h[t];
+    umax = std::max(umax, h[t]);
+    emax = std::max<int>(emax, rp[std::min<int64_t>(N, (t + 1) * TR)] - rp[t * TR]);
+  }
+  if (umax > 65535) return;  // union positions are 16-bit
+  DBuf<int32_t> tptr(nt + 1), tcol(std::max<int32_t>(ptr[nt], 1));
+  DBuf<uint16_t> lcol(std::max<int64_t>(P->nnzb, 1));
+  NM_HIP(hipMemcpyAsync(tptr.p, ptr.data(), 4 * (nt + 1), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_group_union, dim3((unsigned)nt), dim3(256), 0, st, N, TR, P->row_ptr.p, P->col.p, 1, nullptr,
+                     tptr.p, tcol.p, lcol.p);
+  NM_HIP(hipStreamSynchronize(st));
+  P->tile_rows = TR;
+  P->tile_umax = umax;
+  P->tile_emax = emax;
+  P->tile_ptr = std::move(tptr);
+  P->tile_col = std::move(tcol);
+  P->tile_lcol = std::move(lcol);
+}
+
 }  // namespace nm

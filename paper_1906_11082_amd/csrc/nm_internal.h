@@ -153,7 +153,15 @@ struct nm_pencil {
   nm::DBuf<double> grp_coef;
   nm::DBuf<float> grp_coef32;  // FP32 shadow (built with the other FP32 shadows)
   int grouped = 1;  // 0: per-row kernels only; 1: grouped from 32 columns; 2: grouped at any width
+  // LDS tiles of the node graph (tiled mass solve): tile_rows consecutive internal rows, the
+  // sorted union of their columns, and each nonzero's position in its tile's union;
+  // tile_umax / tile_emax: largest union and largest entry count of a tile (0: no tiles)
+  int tile_rows = 0, tile_umax = 0, tile_emax = 0;
+  int tiled = 0;  // 0: off (default); 1: tiles where they fit
+  nm::DBuf<int32_t> tile_ptr, tile_col;
+  nm::DBuf<uint16_t> tile_lcol;
   int tuned_block = 0;  // block width chosen by the autotuner (0: none)
+  int tuned_tile = 0;   // tile rows chosen by the autotuner (0: none or no tiles)
   rocblas_handle blas = nullptr;
   std::mutex fp32_mx;  // the window threads of one pencil create the FP32 shadows once
   void ensure_fp32(hipStream_t st);
@@ -162,8 +170,10 @@ struct nm_pencil {
 namespace nm {
 // pattern + assembly (nm_assemble.hip)
 void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStream_t st);
-// row groups (nm_groups.hip)
+// row groups and LDS tiles (nm_groups.hip)
 void build_row_groups(nm_pencil* P, hipStream_t st);
+// tiles of `rows` rows (0: NM_TILE_ROWS or 32, and NM_TILES=0 switches them off)
+void build_tiles(nm_pencil* P, hipStream_t st, int rows = 0);
 
 // operators (nm_ops.hip)
 // Sampled HIP-event timing of the hot kernel (a middle Chebyshev-Jacobi
@@ -190,11 +200,26 @@ struct ApplyCfg {
   KernelProf* prof = nullptr;
 };
 int cheb_steps(double lo, double hi, double tol);
+// kernel of the middle mass-solve steps on b columns (FP32 or FP64 steps): 0 per-row, 1 row groups,
+// 2 LDS tiles
+int mass_kernel_kind(const nm_pencil* P, int b, bool fp32);
 // sets cfg.mixP / mixK for `passes` (0 or 2..8; FP64 filters only) from the overall
 // bound mtol, or kM_pass steps per pass when > 0; creates the FP32 shadows it reads
 void set_mass_passes(nm_pencil* P, ApplyCfg& cfg, int passes, double mtol, int kM_pass, hipStream_t st);
 // fastest block width and mass-solve kernel for this pencil (sets tuned_block and grouped)
 void autotune(nm_pencil* P, int precision, hipStream_t st, int* best_b, double* best_us_per_col);
+// work buffers of apply_op_ws for op on b columns: nvec vectors of `vec` elements,
+// then npres vectors of `pres` elements (elements of the operator's precision)
+struct OpWorkElems {
+  size_t vec = 0, pres = 0;
+  int nvec = 0, npres = 0;
+  size_t elems() const { return vec * nvec + pres * npres; }
+};
+OpWorkElems op_work_elems(const nm_pencil* P, int op, int b);
+// Y = op(X) in the internal node order with the work buffers in `work` (op_work_elems; no
+// allocation, no synchronisation; FP32 operators need the FP32 matrices to exist; no mixed solve)
+void apply_op_ws(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg, void* work,
+                 hipStream_t st);
 // operators on vectors in the internal node order
 void apply_op(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg,
               hipStream_t st);
@@ -205,6 +230,12 @@ void api_apply(const nm_pencil* P, int op, int ncols, const void* X, void* Y, co
 void permute_rows(int64_t rows, int w, const void* src, void* dst, const int32_t* map, int elem_bytes,
                   hipStream_t st);
 
+// work buffers of one B application: f, ya, yb [N][3b]; pt, pa, pb [n_p][b]
+template <class T>
+struct BWork {
+  T *f = nullptr, *ya = nullptr, *yb = nullptr, *pt = nullptr, *pa = nullptr, *pb = nullptr;
+};
+
 // workspace for filter applications on a block of ncols columns
 template <class T>
 struct FilterWork {
@@ -214,6 +245,7 @@ struct FilterWork {
   DBuf<float> s0, s1, s2, s3;  // FP32 right-hand side, iterates and first result of the mixed mass solve
   void ensure(const nm_pencil* P, int ncols);
   void ensure_mixed(const nm_pencil* P, int ncols);
+  BWork<T> bwork() const { return BWork<T>{f.p, ya.p, yb.p, pt.p, pa.p, pb.p}; }
 };
 template <class T>
 void filter_apply(const nm_pencil* P, const double* mu, int m, double c, double e, double l0,
@@ -227,6 +259,10 @@ template <class T>
 void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cfg, FilterWork<T>& w,
              hipStream_t st);
 
+// density of states: tau_k = (1/s) sum_v z_v . T_k((B - c)/e) z_v, k = 0..m (host tau[m+1]),
+// Z device [n][s] in the internal node order
+void dos_traces(const nm_pencil* P, double lmin, double lmax, int m, int s, const double* Z, const ApplyCfg& cfg,
+                hipStream_t st, double* tau);
 // column dot products out[v] = sum_r X[r*ldx+v] Y[r*ldy+v] (deterministic)
 void col_dots(int64_t rows, int ncols, const double* X, int ldx, const double* Y, int ldy,
               double* out_dev, hipStream_t st);

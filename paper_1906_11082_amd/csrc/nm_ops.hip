@@ -560,6 +560,153 @@ __global__ __launch_bounds__(256) void k_cj_group(
   }
 }
 
+// LDS-tiled Chebyshev-Jacobi step (same arithmetic, modes and summation
+// order as k_cj_step, so the results are bit-identical).  A workgroup owns
+// one tile of TR = 256 / LPR consecutive Morton rows and one chunk of
+// C = LPR * V consecutive entries of the row width w (V entries = 16 bytes
+// per lane); each group of LPR lanes owns one row of the tile:
+//   0. the own row's stream operands (f, y_prev, y, and the filter's) are
+//      loaded first, so their latency overlaps the staging;
+//   1. the chunk of every row in the tile's column union is gathered once
+//      (LPR lanes per union row, 16-byte loads: first all union indices of
+//      the lane, then all its chunks, all in flight together) and written to
+//      LDS, next to the tile's CSR entries (16-bit union positions, values);
+//   2. each row's sum runs from LDS in CSR order, then the update.
+// A tile's union holds ~6.7 rows per row at TR = 32 against ~27.7 nonzeros
+// per row, so neighbour chunks are read from L2 ~4x less often than by
+// per-row gathers, as whole 64/128-byte segments.  Consecutive workgroups are
+// the chunks of one tile (its entries stay in L2).  MAXJ and MAXE bound the
+// union and the entries: U <= MAXJ * TR, E <= MAXE * 256 (launch plan).
+template <class T, int LPR, int MAXJ, int MAXE>
+__global__ __launch_bounds__(256) void k_cj_tile(
+    uint32_t N, uint32_t w, int nch, int ucap, int ecap, const int32_t* __restrict__ tptr,
+    const int32_t* __restrict__ tcol, const int32_t* __restrict__ rp, const uint16_t* __restrict__ lcol,
+    const T* __restrict__ val, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
+    const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
+    T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout, T* Yacc) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int C = LPR * V;
+  constexpr int TR = 256 / LPR;
+  extern __shared__ float4 nm_tile_smem[];
+  T* xs = reinterpret_cast<T*>(nm_tile_smem);                  // [ucap][C]
+  T* s_val = xs + (size_t)ucap * C;                             // [ecap]
+  uint16_t* s_lc = reinterpret_cast<uint16_t*>(s_val + ecap);  // [ecap]
+  const uint32_t bid = (uint32_t)nm_xcd_block();
+  const uint32_t tile = bid / (uint32_t)nch, ch = bid - tile * (uint32_t)nch;
+  const uint32_t ntiles = (N + TR - 1) / TR;
+  if (tile >= ntiles) return;  // grid padding: the whole workgroup leaves before any barrier
+  const uint32_t r0 = tile * TR, r1 = min(N, r0 + (uint32_t)TR);
+  const int32_t u0 = tptr[tile], U = tptr[tile + 1] - u0;
+  const int32_t kb = rp[r0], E = rp[r1] - kb;
+  const uint32_t lane = threadIdx.x % LPR, slot = threadIdx.x / LPR;
+  const uint32_t e = ch * C + lane * V;  // entry of this lane within a row
+  const uint32_t row = r0 + slot;
+  const bool has = row < r1;
+  const size_t o = (size_t)row * w + e;
+  // 0. own-row operands (rows past the tile's end re-read its last row, a
+  // valid address; loads are unconditional so no branch forces a wait)
+  const uint32_t rowc = min(row, r1 - 1);
+  const size_t oc = (size_t)rowc * w + e;
+  const int32_t k0 = rp[rowc] - kb, k1 = rp[rowc + 1] - kb;
+  const T dr = dinv[rowc];
+  const Vx<T, V> ff = ldv_nt<T, V>(f + oc);
+  const Vx<T, V> yp = ldv_nt<T, V>((prev_zero ? f : yprev) + oc);  // prev_zero: not used below
+  const Vx<T, V> yc = ldv<T, V>(ycur + oc);
+  Vx<T, V> wi, wp, yy;
+  if (mode != 0) {  // uniform over the launch
+    wi = ldv<T, V>(win + oc);
+    wp = ldv<T, V>((a2 != T(0) ? wprev : win) + oc);
+    yy = ldv<T, V>((ymode == 2 ? Yacc : win) + oc);
+  }
+  // 1. union indices, the tile's CSR entries (E <= MAXE * 256) and the union
+  // chunks, all in flight before the LDS writes.  Loads are unconditional
+  // (positions past the union or the entries re-read the last one, a valid
+  // address) so that no branch forces a wait between them; only the LDS
+  // writes are predicated.
+  uint32_t ci[MAXJ];
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) ci[j] = (uint32_t)tcol[u0 + min((int32_t)slot + j * TR, U - 1)];
+  T vv[MAXE];
+  uint16_t ll[MAXE];
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int32_t i = min((int32_t)threadIdx.x + q * 256, E - 1);
+    vv[q] = val[kb + i];
+    ll[q] = lcol[kb + i];
+  }
+  Vx<T, V> xb[MAXJ];
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) xb[j] = ldv<T, V>(ycur + (size_t)ci[j] * w + e);
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int32_t i = (int32_t)threadIdx.x + q * 256;
+    if (i < E) {
+      s_val[i] = vv[q];
+      s_lc[i] = ll[q];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) {
+    const int32_t i = (int32_t)slot + j * TR;
+    if (i < U) stv<T, V>(xs + (size_t)i * C + lane * V, xb[j]);
+  }
+  __syncthreads();
+  if (!has) return;
+  // 2. the row's sum from LDS in CSR order, then the update
+  Vx<T, V> acc;
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+  int32_t k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    T a[4];
+    Vx<T, V> x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = s_val[k + u];
+      x[u] = ldv<T, V>(xs + (size_t)s_lc[k + u] * C + lane * V);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc.v[i] += a[u] * x[u].v[i];
+  }
+  for (; k < k1; ++k) {
+    const T a = s_val[k];
+    const Vx<T, V> x = ldv<T, V>(xs + (size_t)s_lc[k] * C + lane * V);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc.v[i] += a * x.v[i];
+  }
+  const T bd = beta * dr;
+  Vx<T, V> z;
+#pragma unroll
+  for (int i = 0; i < V; ++i)
+    z.v[i] = yc.v[i] + alpha * (yc.v[i] - (prev_zero ? T(0) : yp.v[i])) + bd * (ff.v[i] - acc.v[i]);
+  if (mode == 0) {
+    stv_nt<T, V>(out + o, z);
+    return;
+  }
+  Vx<T, V> wo;
+#pragma unroll
+  for (int i = 0; i < V; ++i) wo.v[i] = a1 * (z.v[i] - cs * wi.v[i]);
+  if (a2 != T(0)) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) wo.v[i] += a2 * wp.v[i];
+  }
+  stv<T, V>(wout + o, wo);
+  if (ymode == 0) return;
+  T m0[V], m1[V];
+  series_coef<T, V>(mu0, mu, mu0c, muc, e % (w / 3), m0, m1);
+  if (ymode == 1) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) yy.v[i] = m0[i] * wi.v[i] + m1[i] * wo.v[i];
+    stv<T, V>(Yacc + o, yy);
+  } else if (ymode == 2) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) yy.v[i] += m1[i] * wo.v[i];
+    stv<T, V>(Yacc + o, yy);
+  }
+}
+
 // ---- mass solve in FP32 passes with FP64 residual corrections
 // (iterative refinement of the Chebyshev-Jacobi solve): with r_0 = f, pass p
 // solves M y_p = r_{p-1} in FP32 and r_p = r_{p-1} - M y_p is formed in FP64
@@ -797,6 +944,68 @@ GroupPlan group_plan(const nm_pencil* P, int b) {
   return tp;
 }
 
+// LDS-tile launch plan: tiles of 32 rows read rows in 128-byte chunks (8
+// lanes per row), tiles of 64 rows in 64-byte chunks (4 lanes); the chunk
+// must divide the row, the largest union must fit MAXJ chunks per row slot
+// and the workgroup's LDS (the largest union's chunks and the largest
+// tile's CSR entries) must stay within 64 KB.
+constexpr int TILE_MAXJ = 16;
+struct TilePlan {
+  bool on = false;
+  int TR = 0, lpr = 0, nch = 0, ucap = 0, ecap = 0;
+  size_t lds = 0;
+};
+template <class T>
+TilePlan tile_plan(const nm_pencil* P, int b) {
+  TilePlan t;
+  if (!P->tiled || b < 1 || (P->tile_rows != 32 && P->tile_rows != 64)) return t;
+  const size_t rowb = (size_t)3 * b * sizeof(T);
+  const int lpr = 256 / P->tile_rows;
+  const size_t chunk = (size_t)lpr * 16;
+  if (rowb % chunk != 0) return t;
+  if (P->tile_umax > TILE_MAXJ * P->tile_rows) return t;
+  if (P->tile_emax > (P->tile_rows == 32 ? 8 : 12) * 256) return t;
+  t.ucap = P->tile_umax;
+  t.ecap = (P->tile_emax + 7) / 8 * 8;
+  t.lds = t.ucap * chunk + (size_t)t.ecap * (sizeof(T) + 2);
+  if (t.lds > 65536) return t;
+  t.on = true;
+  t.TR = P->tile_rows;
+  t.lpr = lpr;
+  t.nch = (int)(rowb / chunk);
+  return t;
+}
+
+template <class T>
+void launch_cj_tile(const nm_pencil* P, const TilePlan& tp, const T* val, int64_t N, int w, const T* dinv,
+                    const T* f, const T* ycur, const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out,
+                    const T* win, const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, const T* mu0c,
+                    const T* muc, T* wout, T* Yacc, hipStream_t st) {
+  const int64_t ntiles = (N + tp.TR - 1) / tp.TR;
+  const int64_t wgs = ntiles * tp.nch;
+  unsigned g = (unsigned)((wgs + 7) / 8 * 8);
+#define NM_TILE(LPR, MJ, ME)                                                                                      \
+  hipLaunchKernelGGL((k_cj_tile<T, LPR, MJ, ME>), dim3(g), dim3(256), tp.lds, st, (uint32_t)N, (uint32_t)w, tp.nch, \
+                     tp.ucap, tp.ecap, P->tile_ptr.p, P->tile_col.p, P->row_ptr.p, P->tile_lcol.p, val, dinv, f,   \
+                     ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, mu0, mu, mu0c, \
+                     muc, wout, Yacc)
+  const int mj = (tp.ucap + tp.TR - 1) / tp.TR, me = (tp.ecap + 255) / 256;
+  if (tp.lpr == 8) {
+    if (mj <= 8) {
+      if (me <= 4) NM_TILE(8, 8, 4); else NM_TILE(8, 8, 8);
+    } else {
+      if (me <= 4) NM_TILE(8, 16, 4); else NM_TILE(8, 16, 8);
+    }
+  } else {
+    if (mj <= 8) {
+      if (me <= 8) NM_TILE(4, 8, 8); else NM_TILE(4, 8, 12);
+    } else {
+      if (me <= 8) NM_TILE(4, 16, 8); else NM_TILE(4, 16, 12);
+    }
+  }
+#undef NM_TILE
+}
+
 template <class T>
 void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const T* f, const T* ycur, const T* yprev,
                      T alpha, T beta, int prev_zero, int mode, T* out, const T* win, const T* wprev, T a1, T cs, T a2,
@@ -816,12 +1025,36 @@ void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const
 #undef NM_GRP
 }
 
+// Chebyshev-Jacobi step of the displacement mass solve: LDS tiles where
+// they apply, else row groups, else one row per lane.  Pressure (K_p)
+// solves pass no plans and take the per-row kernel.
+template <class T>
+struct MassPlan {
+  const nm_pencil* P = nullptr;
+  TilePlan tile;
+  GroupPlan group;
+};
+template <class T>
+MassPlan<T> mass_plan(const nm_pencil* P, int b) {
+  MassPlan<T> m;
+  m.P = P;
+  m.tile = tile_plan<T>(P, b);
+  if (!m.tile.on) m.group = group_plan<T>(P, b);
+  return m;
+}
+
 template <class T>
 void launch_cj_step(int64_t rows, int w, const int32_t* rp, const int32_t* col, const T* val, const T* dinv,
                     const T* f, const T* ycur, const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out,
                     const T* win, const T* wprev, T a1, T cs, T a2, int ymode, T mu0, T mu, T* wout, T* Yacc,
-                    hipStream_t st, const GroupPlan* tp = nullptr, const T* mu0c = nullptr,
+                    hipStream_t st, const MassPlan<T>* mp = nullptr, const T* mu0c = nullptr,
                     const T* muc = nullptr) {
+  if (mp && mp->tile.on) {
+    launch_cj_tile<T>(mp->P, mp->tile, val, rows, w, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win,
+                      wprev, a1, cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc, st);
+    return;
+  }
+  const GroupPlan* tp = mp ? &mp->group : nullptr;
   if (tp && tp->on) {
     launch_cj_group<T>(*tp, rows, w, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1, cs,
                        a2, ymode, mu0, mu, mu0c, muc, wout, Yacc, st);
@@ -898,13 +1131,13 @@ T* kp_solve(const nm_pencil* P, int b, const T* t, int kP, T* pa, T* pb, hipStre
 
 // F = A X (Cowling operator) and optionally Y1 = D^{-1} F / theta
 template <class T>
-void a_apply(const nm_pencil* P, int b, const T* X, T* F, T* Y1, double inv_theta, int kP, FilterWork<T>& w,
+void a_apply(const nm_pencil* P, int b, const T* X, T* F, T* Y1, double inv_theta, int kP, const BWork<T>& w,
              hipStream_t st) {
   auto m = mats<T>(P);
   const T* S = nullptr;
   if (P->n_pres > 0) {
-    LAUNCH(k_egt<T>, P->n_pres * b, st, P->n_pres, b, P->egt_ptr.p, P->egt_col.p, m.egt, X, w.pt.p);
-    S = kp_solve<T>(P, b, w.pt.p, kP, w.pa.p, w.pb.p, st);
+    LAUNCH(k_egt<T>, P->n_pres * b, st, P->n_pres, b, P->egt_ptr.p, P->egt_col.p, m.egt, X, w.pt);
+    S = kp_solve<T>(P, b, w.pt, kP, w.pa, w.pb, st);
   }
   launch_apply_ag<T>(P->N, b, P->row_ptr.p, P->col.p, m.ag, X, P->eg_ptr.p, P->eg_col.p, m.eg, S, F, m.mdinv,
                      (T)inv_theta, Y1, st);
@@ -937,7 +1170,7 @@ void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, con
   NM_REQUIRE(P->ms32.p && P->mdinv32.p, NM_EINVAL, "mixed mass solve without the FP32 matrix shadows");
   const auto m64 = mats<double>(P);
   const auto m32 = mats<float>(P);
-  const GroupPlan tp = group_plan<float>(P, b);
+  const MassPlan<float> tp = mass_plan<float>(P, b);
   const ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, cfg.mixK);
   const int64_t N = P->N;
   const int wd = 3 * b;
@@ -992,43 +1225,37 @@ void mass_solve_mixed(const nm_pencil* P, int b, const double* f, double* Z, con
 #undef NM_MIX
 }
 
-// z = S_M(A X); either written to Z or consumed by the filter update u
+// z = S_M(A X) with one Chebyshev-Jacobi pass in T; either written to Z or
+// consumed by the filter update u.  Work buffers: w.f, w.ya, w.yb [N][3b],
+// the pressure buffers [n_p][b].
 template <class T>
-void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, const ApplyCfg& cfg,
-                  FilterWork<T>& w, hipStream_t st, KernelProf* prof = nullptr) {
+void b_apply_ws(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, const ApplyCfg& cfg,
+                const BWork<T>& w, hipStream_t st, KernelProf* prof = nullptr) {
   const int kM = cfg.kM, kP = cfg.kP;
   NM_REQUIRE(kM >= 2, NM_EINVAL, "the M solve needs at least 2 Chebyshev steps");
-  if constexpr (std::is_same<T, double>::value) {
-    if (cfg.mixP > 0) {
-      w.ensure_mixed(P, b);
-      a_apply<double>(P, b, X, w.f.p, nullptr, 0.0, kP, w, st);
-      mass_solve_mixed(P, b, w.f.p, Z, u, cfg, MixBufs{w.ya.p, w.yb.p, {w.s0.p, w.s1.p, w.s2.p, w.s3.p}}, st, prof);
-      return;
-    }
-  }
   auto m = mats<T>(P);
   ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, kM);
-  const GroupPlan tp = group_plan<T>(P, b);
-  a_apply<T>(P, b, X, w.f.p, w.ya.p, 1.0 / cc.theta, kP, w, st);
+  const MassPlan<T> tp = mass_plan<T>(P, b);
+  a_apply<T>(P, b, X, w.f, w.ya, 1.0 / cc.theta, kP, w, st);
   const int64_t N = P->N;
   const int wd = 3 * b;
-  T *cur = w.ya.p, *prev = w.yb.p;
+  T *cur = w.ya, *prev = w.yb;
   for (int j = 1; j < kM; ++j) {
     bool last = j == kM - 1;
     if (!last) {
       bool sampled = false;
       if (prof && j >= 2) prof->before(st, sampled);
-      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
+      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, prev, nullptr, nullptr, T(0), T(0), T(0), 0, T(0),
                         T(0), nullptr, nullptr, st, &tp);
       if (sampled) prof->after(st);
       std::swap(cur, prev);
     } else if (!u.on) {
-      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
+      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 0, Z, nullptr, nullptr, T(0), T(0), T(0), 0, T(0), T(0),
                         nullptr, nullptr, st, &tp);
     } else {
-      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f.p, cur, prev, (T)cc.alpha[j - 1],
+      launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, w.f, cur, prev, (T)cc.alpha[j - 1],
                         (T)cc.beta[j - 1], j == 1 ? 1 : 0, 1, nullptr, (const T*)u.win, (const T*)u.wprev, (T)u.a1,
                         (T)u.cs, (T)u.a2, u.ymode, (T)u.mu0, (T)u.mu, (T*)u.wout, (T*)u.Y, st, &tp,
                         (const T*)u.mu0c, (const T*)u.muc);
@@ -1036,7 +1263,32 @@ void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, 
   }
 }
 
+// z = S_M(A X); either written to Z or consumed by the filter update u
+template <class T>
+void b_apply_impl(const nm_pencil* P, int b, const T* X, T* Z, const Update& u, const ApplyCfg& cfg,
+                  FilterWork<T>& w, hipStream_t st, KernelProf* prof = nullptr) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (cfg.mixP > 0) {
+      NM_REQUIRE(cfg.kM >= 2, NM_EINVAL, "the M solve needs at least 2 Chebyshev steps");
+      w.ensure_mixed(P, b);
+      a_apply<double>(P, b, X, w.f.p, nullptr, 0.0, cfg.kP, w.bwork(), st);
+      mass_solve_mixed(P, b, w.f.p, Z, u, cfg, MixBufs{w.ya.p, w.yb.p, {w.s0.p, w.s1.p, w.s2.p, w.s3.p}}, st, prof);
+      return;
+    }
+  }
+  b_apply_ws<T>(P, b, X, Z, u, cfg, w.bwork(), st, prof);
+}
+
 }  // namespace
+
+int mass_kernel_kind(const nm_pencil* P, int b, bool fp32) {
+  if (fp32) {
+    const MassPlan<float> m = mass_plan<float>(P, b);
+    return m.tile.on ? 2 : (m.group.on ? 1 : 0);
+  }
+  const MassPlan<double> m = mass_plan<double>(P, b);
+  return m.tile.on ? 2 : (m.group.on ? 1 : 0);
+}
 
 int cheb_steps(double lo, double hi, double tol) {
   double kap = hi / lo;
@@ -1165,10 +1417,62 @@ void filter_apply_cols(const nm_pencil* P, const double* mu_cols, int m, double 
   NM_HIP(hipStreamSynchronize(st));
 }
 
+// Density of states (kernel polynomial method): tau_k = (1/s) sum_v
+// z_v . T_k((B - c)/e) z_v for k = 0..m from the s columns of Z (internal
+// node order), by the filter's three-term recurrence (update fused into the
+// mass solve, no series accumulation) with the column dots of each step
+// reduced on the device in a fixed order.
+void dos_traces(const nm_pencil* P, double lmin, double lmax, int m, int s, const double* Z, const ApplyCfg& cfg,
+                hipStream_t st, double* tau) {
+  check_block(3 * P->N, s);
+  NM_REQUIRE(m >= 0 && lmax > lmin, NM_EINVAL, "need m >= 0 and lmax > lmin");
+  const int64_t n = 3 * P->N;
+  const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
+  FilterWork<double> w;
+  w.ensure(P, s);
+  const int nblk = 512;
+  DBuf<double> dots((size_t)(m + 1) * s), part((size_t)nblk * s);
+  const int64_t rows_per = (n + nblk - 1) / nblk;
+  auto coldot = [&](const double* W, int k) {
+    hipLaunchKernelGGL(k_coldot_partial, dim3(nblk), dim3(256), 0, st, n, s, Z, s, W, s, rows_per, part.p);
+    hipLaunchKernelGGL(k_coldot_final, dim3((s + 63) / 64), dim3(64), 0, st, nblk, s, part.p, dots.p + (size_t)k * s);
+  };
+  coldot(Z, 0);
+  double* bufs[2] = {w.w0.p, w.w1.p};
+  const double* wprev = nullptr;
+  const double* win = Z;
+  for (int k = 1; k <= m; ++k) {
+    double* out = (wprev == bufs[0] || wprev == bufs[1]) ? (double*)wprev : (win == bufs[0] ? bufs[1] : bufs[0]);
+    Update u;
+    u.on = true;
+    u.win = win;
+    u.wprev = k >= 2 ? wprev : nullptr;
+    u.a1 = (k == 1 ? 1.0 : 2.0) / e;
+    u.cs = c;
+    u.a2 = k == 1 ? 0.0 : -1.0;
+    u.ymode = 0;
+    u.wout = out;
+    b_apply_impl<double>(P, s, win, nullptr, u, cfg, w, st);
+    coldot(out, k);
+    wprev = win;
+    win = out;
+  }
+  std::vector<double> h((size_t)(m + 1) * s);
+  NM_HIP(hipMemcpyAsync(h.data(), dots.p, 8 * h.size(), hipMemcpyDeviceToHost, st));
+  NM_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k <= m; ++k) {
+    double t = 0;
+    for (int v = 0; v < s; ++v) t += h[(size_t)k * s + v];
+    tau[k] = t / s;
+  }
+}
+
 // Autotuning of the mass-solve step, the hot loop of every filter step: for
-// block widths b in {8, 16, 32, 64} and, in FP64, the per-row and row-group
-// kernels, time `reps` middle Chebyshev-Jacobi steps with HIP events and keep
-// the fastest per column.  Sets the pencil's row-group mode to the winner's.
+// block widths b in {8, 16, 32, 64} and every kernel -- one row per lane,
+// row groups, and LDS tiles of 32 or 64 rows (the block size of the tiled
+// sparse format) -- time `reps` middle Chebyshev-Jacobi steps with
+// HIP events and keep the fastest per column.  Sets the pencil's kernel
+// choice (and rebuilds its tiles at the winning size).
 template <class T>
 static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_us) {
   auto m = mats<T>(P);
@@ -1181,15 +1485,28 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
   hipEvent_t e0, e1;
   NM_HIP(hipEventCreate(&e0));
   NM_HIP(hipEventCreate(&e1));
-  const int saved = P->grouped;
   double best = 1e300;
-  int bb = 16, bg = saved;
-  const int modes[2] = {0, 2};
-  for (int b : {8, 16, 32, 64}) {
-    for (int gm : modes) {
-      if (gm == 2 && (sizeof(T) != 8 || P->grp_rows <= 0)) continue;
-      P->grouped = gm;
-      const GroupPlan tp = group_plan<T>(P, b);
+  int bb = 16, bgrp = P->grouped, btile = 0;
+  // candidate kernels: (tile rows, grouped mode); tile rows 0 = no tiles
+  struct Cand {
+    int tr, grouped;
+  };
+  std::vector<Cand> cands = {{0, 0}};
+  if (P->grp_rows > 0) cands.push_back({0, 2});
+  for (int tr : {32, 64}) cands.push_back({tr, 0});
+  const char* venv = getenv("NM_AUTOTUNE_VERBOSE");
+  const bool verbose = venv && atoi(venv) != 0;
+  for (const Cand& cd : cands) {
+    if (cd.tr > 0) {
+      build_tiles(P, st, cd.tr);
+      if (P->tile_rows != cd.tr) continue;  // this tile size does not fit
+    } else {
+      P->tiled = 0;
+    }
+    P->grouped = cd.grouped;
+    for (int b : {8, 16, 32, 64}) {
+      const MassPlan<T> tp = mass_plan<T>(P, b);
+      if (cd.tr > 0 && !tp.tile.on) continue;
       const int wd = 3 * b;
       auto step = [&]() {
         launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, f.p, y0.p, y1.p, T(0.5), T(0.1), 0, 0, y1.p,
@@ -1204,17 +1521,28 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
       float ms = 0;
       NM_HIP(hipEventElapsedTime(&ms, e0, e1));
       const double us = 1e3 * ms / reps / b;
+      if (verbose)
+        fprintf(stderr, "[autotune] %s b=%d kernel=%s tile_rows=%d: %.1f us per step, %.3f us per column\n",
+                sizeof(T) == 8 ? "fp64" : "fp32", b, tp.tile.on ? "tile" : (tp.group.on ? "group" : "row"), cd.tr,
+                1e3 * ms / reps, us);
       if (us < best) {
         best = us;
         bb = b;
-        bg = gm;
+        bgrp = cd.grouped;
+        btile = cd.tr;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  P->grouped = bg;
+  if (btile > 0) {
+    build_tiles(P, st, btile);
+  } else {
+    P->tiled = 0;
+  }
+  P->grouped = bgrp;
   P->tuned_block = bb;
+  P->tuned_tile = btile;
   *best_b = bb;
   *best_us = best;
 }
@@ -1244,9 +1572,12 @@ template void filter_apply<double>(const nm_pencil*, const double*, int, double,
 template void filter_apply<float>(const nm_pencil*, const double*, int, double, double, double, double, int,
                                   const float*, float*, const ApplyCfg&, FilterWork<float>&, hipStream_t);
 
+// Y = op(X) with caller-provided work buffers (see op_work_elems); stream
+// ordered, no synchronisation and no allocation.  The mixed-precision mass
+// solve (cfg.mixP) is not available here.
 template <class T>
-static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* Yv, const ApplyCfg& cfg,
-                       hipStream_t st) {
+static void apply_op_ws_t(const nm_pencil* P, int op, int b, const void* Xv, void* Yv, const ApplyCfg& cfg,
+                          const BWork<T>& w, hipStream_t st) {
   const T* X = (const T*)Xv;
   T* Y = (T*)Yv;
   auto m = mats<T>(P);
@@ -1278,38 +1609,20 @@ static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* 
       break;
     case NM_OP_KPINV: {
       NM_REQUIRE(NP > 0, NM_EINVAL, "pencil has no pressure unknowns");
-      DBuf<T> pa(NP * b), pb(NP * b);
-      T* r = kp_solve<T>(P, b, X, cfg.kP, pa.p, pb.p, st);
+      NM_REQUIRE(cfg.kP >= 1, NM_EINVAL, "kP must be >= 1");
+      T* r = kp_solve<T>(P, b, X, cfg.kP, w.pa, w.pb, st);
       NM_HIP(hipMemcpyAsync(Y, r, NP * b * sizeof(T), hipMemcpyDeviceToDevice, st));
-      NM_HIP(hipStreamSynchronize(st));
       break;
     }
-    case NM_OP_A: {
-      // only the pressure-sized buffers of the Schur part are used
-      FilterWork<T> w;
-      const size_t np = (size_t)std::max<int64_t>(NP, 1) * b;
-      w.pt.alloc(np); w.pa.alloc(np); w.pb.alloc(np);
+    case NM_OP_A:
       a_apply<T>(P, b, X, Y, nullptr, 0.0, cfg.kP, w, st);
-      NM_HIP(hipStreamSynchronize(st));
       break;
-    }
     case NM_OP_MINV: {
-      if constexpr (std::is_same<T, double>::value) {
-        if (cfg.mixP > 0) {
-          const size_t n = (size_t)N * wd;
-          DBuf<double> r64(n), acc(n);
-          DBuf<float> s0(n), s1(n), s2(n), s3(n);
-          mass_solve_mixed(P, b, X, Y, Update{}, cfg, MixBufs{r64.p, acc.p, {s0.p, s1.p, s2.p, s3.p}}, st, nullptr);
-          NM_HIP(hipStreamSynchronize(st));
-          break;
-        }
-      }
       NM_REQUIRE(cfg.kM >= 2, NM_EINVAL, "kM must be >= 2");
-      DBuf<T> ya(N * wd), yb(N * wd);
       ChebCoef cc = cheb_coef(P->ref.m_lo, P->ref.m_hi, cfg.kM);
-      const GroupPlan tp = group_plan<T>(P, b);
-      launch_cj_first<T>(N, wd, m.mdinv, X, (T)(1.0 / cc.theta), ya.p, st);
-      T *cur = ya.p, *prev = yb.p;
+      const MassPlan<T> tp = mass_plan<T>(P, b);
+      launch_cj_first<T>(N, wd, m.mdinv, X, (T)(1.0 / cc.theta), w.ya, st);
+      T *cur = w.ya, *prev = w.yb;
       for (int j = 1; j < cfg.kM; ++j) {
         T* out = j == cfg.kM - 1 ? Y : prev;
         launch_cj_step<T>(N, wd, P->row_ptr.p, P->col.p, m.ms, m.mdinv, X, cur, prev, (T)cc.alpha[j - 1],
@@ -1317,19 +1630,57 @@ static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* 
                           T(0), nullptr, nullptr, st, &tp);
         std::swap(cur, prev);
       }
-      NM_HIP(hipStreamSynchronize(st));
       break;
     }
-    case NM_OP_B: {
-      FilterWork<T> w;
-      b_apply<T>(P, b, X, Y, cfg, w, st);
-      NM_HIP(hipStreamSynchronize(st));
+    case NM_OP_B:
+      b_apply_ws<T>(P, b, X, Y, Update{}, cfg, w, st);
       break;
-    }
     default:
       throw Error(NM_EINVAL, "unknown operator " + std::to_string(op));
   }
   NM_HIP(hipGetLastError());
+}
+
+template <class T>
+static void apply_op_t(const nm_pencil* P, int op, int b, const void* Xv, void* Yv, const ApplyCfg& cfg,
+                       hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (op == NM_OP_MINV && cfg.mixP > 0) {
+      const size_t n = (size_t)P->N * 3 * b;
+      DBuf<double> r64(n), acc(n);
+      DBuf<float> s0(n), s1(n), s2(n), s3(n);
+      mass_solve_mixed(P, b, (const double*)Xv, (double*)Yv, Update{}, cfg,
+                       MixBufs{r64.p, acc.p, {s0.p, s1.p, s2.p, s3.p}}, st, nullptr);
+      NM_HIP(hipStreamSynchronize(st));
+      NM_HIP(hipGetLastError());
+      return;
+    }
+    if (op == NM_OP_B && cfg.mixP > 0) {
+      FilterWork<double> fw;
+      b_apply<double>(P, b, (const double*)Xv, (double*)Yv, cfg, fw, st);
+      NM_HIP(hipStreamSynchronize(st));
+      return;
+    }
+  }
+  OpWorkElems need = op_work_elems(P, op, b);
+  DBuf<T> vec(need.vec * need.nvec), pres(need.pres * need.npres);
+  BWork<T> w;
+  T* v[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < need.nvec; ++i) v[i] = vec.p + (size_t)i * need.vec;
+  if (need.nvec == 3) {
+    w.f = v[0]; w.ya = v[1]; w.yb = v[2];
+  } else if (need.nvec == 2) {
+    w.ya = v[0]; w.yb = v[1];
+  }
+  T* q[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < need.npres; ++i) q[i] = pres.p + (size_t)i * need.pres;
+  if (need.npres == 3) {
+    w.pt = q[0]; w.pa = q[1]; w.pb = q[2];
+  } else if (need.npres == 2) {
+    w.pa = q[0]; w.pb = q[1];
+  }
+  apply_op_ws_t<T>(P, op, b, Xv, Yv, cfg, w, st);
+  NM_HIP(hipStreamSynchronize(st));
 }
 
 template <class T>
@@ -1372,6 +1723,58 @@ void api_apply(const nm_pencil* P, int op, int ncols, const void* X, void* Y, co
   apply_op(P, op, ncols, xin, yout, cfg, st);
   if (out_disp) permute_rows(N, (int)w, yi.p, Y, P->perm.p, eb, st);
   NM_HIP(hipStreamSynchronize(st));
+}
+
+OpWorkElems op_work_elems(const nm_pencil* P, int op, int b) {
+  OpWorkElems e;
+  const size_t vec = (size_t)P->N * 3 * b, pres = (size_t)std::max<int64_t>(P->n_pres, 1) * b;
+  switch (op) {
+    case NM_OP_KPINV:
+      e.pres = pres; e.npres = 2;
+      break;
+    case NM_OP_A:
+      e.pres = pres; e.npres = 3;
+      break;
+    case NM_OP_MINV:
+      e.vec = vec; e.nvec = 2;
+      break;
+    case NM_OP_B:
+      e.vec = vec; e.nvec = 3; e.pres = pres; e.npres = 3;
+      break;
+    default:
+      break;
+  }
+  return e;
+}
+
+void apply_op_ws(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg, void* work,
+                 hipStream_t st) {
+  check_block(3 * P->N, ncols);
+  NM_REQUIRE(cfg.mixP == 0, NM_EINVAL, "the mixed-precision mass solve needs its own work buffers");
+  const OpWorkElems need = op_work_elems(P, op, ncols);
+  auto carve = [&](auto* base, auto& w) {
+    using T = std::remove_pointer_t<decltype(base)>;
+    T* v = base;
+    T* a[3] = {nullptr, nullptr, nullptr};
+    for (int i = 0; i < need.nvec; ++i) a[i] = v + (size_t)i * need.vec;
+    T* pr = v + (size_t)need.nvec * need.vec;
+    T* b[3] = {nullptr, nullptr, nullptr};
+    for (int i = 0; i < need.npres; ++i) b[i] = pr + (size_t)i * need.pres;
+    if (need.nvec == 3) { w.f = a[0]; w.ya = a[1]; w.yb = a[2]; }
+    if (need.nvec == 2) { w.ya = a[0]; w.yb = a[1]; }
+    if (need.npres == 3) { w.pt = b[0]; w.pa = b[1]; w.pb = b[2]; }
+    if (need.npres == 2) { w.pa = b[0]; w.pb = b[1]; }
+  };
+  if (cfg.precision == 1) {
+    NM_REQUIRE(P->ms32.p, NM_EINVAL, "FP32 operators before the pencil's FP32 matrices exist");
+    BWork<float> w;
+    carve((float*)work, w);
+    apply_op_ws_t<float>(P, op, ncols, X, Y, cfg, w, st);
+  } else {
+    BWork<double> w;
+    carve((double*)work, w);
+    apply_op_ws_t<double>(P, op, ncols, X, Y, cfg, w, st);
+  }
 }
 
 void apply_op(const nm_pencil* P, int op, int ncols, const void* X, void* Y, const ApplyCfg& cfg, hipStream_t st) {

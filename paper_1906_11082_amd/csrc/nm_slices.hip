@@ -176,6 +176,7 @@ void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const doubl
     out[i]->hot_ms = fb.prof.samples ? fb.prof.ms / fb.prof.samples : 0.0;
     const double sz = (prec || cfg.mixP) ? 4.0 : 8.0;
     out[i]->hot_bytes = (double)P->nnzb * (4.0 + sz) + 4.0 * (P->N + 1) + sz * P->N + 4.0 * 3 * P->N * ctot * sz;
+    out[i]->hot_kernel = mass_kernel_kind(P, ctot, prec == 1 || cfg.mixP > 0);
   }
   for (int i = 0; i < S; ++i)
     if (errs[i]) {

@@ -141,3 +141,18 @@ def test_block_width_guard(lib):
     with pytest.raises(nm.NMError) as e:
         nm.max_block_columns(0)
     assert e.value.status == -1
+
+
+def test_dos_count_and_slices_match_oracle(lib):
+    """Host-side density-of-states counts and equal-count slice ends equal the
+    oracle's for the same traces (the oracle pins them against exact counts)."""
+    import paper_1906_11082_amd as nm
+    from oracle import dos as D
+    lam = np.sort(np.random.default_rng(5).uniform(0.0, 3.0e3, 900) ** 1.5 / 50.0)
+    lmin, lmax = -0.5, 1.01 * lam.max()
+    tau = D.exact_traces(lam, lmin, lmax, 700)
+    for a, b in [(1.0, 60.0), (5.0, 400.0)]:
+        assert abs(nm.dos_count(tau, lmin, lmax, a, b) - D.window_count(tau, lmin, lmax, a, b)) <= 1e-9 * len(lam)
+        e1 = nm.dos_slices(tau, lmin, lmax, a, b, 4)
+        e2 = D.slice_edges(tau, lmin, lmax, a, b, 4)
+        assert np.abs(e1 - e2).max() <= 1e-9 * b

@@ -76,11 +76,13 @@ def test_mass_solve_within_chebyshev_bound(full):
 
 
 def test_row_groups_match_per_row_at_full_size(full, monkeypatch):
-    """The benchmark's row-group kernel and the per-row kernel give bit-identical
+    """The benchmark's mass-solve kernel (row groups at 32 columns) and the
+    per-row kernel give bit-identical
     mass solves (FP64 and FP32) and filter applications on the full planet at
     32 columns."""
     torch, nm, d, G = full
     monkeypatch.setenv("NM_ROW_GROUPS", "0")
+    monkeypatch.setenv("NM_TILES", "0")
     Gr = nm.Pencil(d)
     n = G.info["n_disp"]
     X = _rand(torch, n, 32, 4)

@@ -179,19 +179,24 @@ def test_assembly_is_deterministic(torch_cuda):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("ncols", [3, 16, 32])
+@pytest.mark.parametrize("ncols", [3, 8, 16, 32])
 def test_row_group_kernel_matches_per_row(torch_cuda, ncols, monkeypatch):
     """The row-group mass-solve kernel (4 or 8 Morton rows per lane, union
-    columns with zero-padded coefficients) sums each row in the same column
-    order as the per-row kernel: FP64 and FP32 results are bit-identical,
-    including the ragged last group."""
+    columns with zero-padded coefficients) and the LDS-tile kernel (32 or 64
+    rows per tile, 128- or 64-byte row chunks) sum each row in the same
+    column order as the per-row kernel: FP64 and FP32 results are
+    bit-identical, including the ragged last group and tile."""
     torch = torch_cuda
     import paper_1906_11082_amd as nm
     d = dict(make_planet("three_layer_planet", n_half=5, order=2, pres_order=1))
     pens = {}
-    for tag, on, R in (("row", "0", "4"), ("g4", "2", "4"), ("g8", "2", "8")):
+    for tag, on, R, tiles, tr in (("row", "0", "4", "0", "32"), ("g4", "2", "4", "0", "32"),
+                                  ("g8", "2", "8", "0", "32"), ("t32", "0", "4", "1", "32"),
+                                  ("t64", "0", "4", "1", "64")):
         monkeypatch.setenv("NM_ROW_GROUPS", on)
         monkeypatch.setenv("NM_GROUP_ROWS", R)
+        monkeypatch.setenv("NM_TILES", tiles)
+        monkeypatch.setenv("NM_TILE_ROWS", tr)
         pens[tag] = nm.Pencil(d)
     N = pens["row"].info["n_node"]
     assert N % 4 != 0 or N % 8 != 0
@@ -202,7 +207,9 @@ def test_row_group_kernel_matches_per_row(torch_cuda, ncols, monkeypatch):
     ref_f = pens["row"].filter_apply(mu, c, e, X, kM=6, kP=5)
     X32 = X.float()
     ref_32 = pens["row"].apply(nm.OP_MINV, X32, kM=17, precision=1)
-    for tag in ("g4", "g8"):
+    N = pens["row"].info["n_node"]
+    assert N % 64 != 0
+    for tag in ("g4", "g8", "t32", "t64"):
         assert torch.equal(pens[tag].apply(nm.OP_MINV, X, kM=17), ref_m), tag
         assert torch.equal(pens[tag].filter_apply(mu, c, e, X, kM=6, kP=5), ref_f), tag
         assert torch.equal(pens[tag].apply(nm.OP_MINV, X32, kM=17, precision=1), ref_32), tag

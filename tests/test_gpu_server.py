@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from conftest import planet as make_planet
+from conftest import planet as make_planet, pencil as oracle_pencil, window_ref, check_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +47,20 @@ def test_server_results_same_alone_and_in_the_mix():
             assert rm.resid.max() <= 1e-8
     assert _overlaps(mix), "no two requests ran concurrently"
     assert not _overlaps(alone)
+    # and against the oracle: dense solves of the balls, shift-invert windows of the layered planet
+    from oracle import solve as S
+    refs = []
+    for name, kw in (("homogeneous_ball", dict(n_half=4, order=1)), ("homogeneous_ball", dict(n_half=3, order=2))):
+        O = oracle_pencil(name, **kw)
+        refs.append((O, S.dense_window(O.AG.toarray(), O.M.toarray(), *(reqs[0 if kw["order"] == 1 else 2][1][0]))))
+    O1, (w1, X1) = refs[0]
+    check_against_oracle(mix[0]["slices"][0], w1, X1, O1.M, rel=1e-9, resid=1e-8, nev=30)
+    O3, (w3, X3) = refs[1]
+    check_against_oracle(mix[2]["slices"][0], w3, X3, O3.M, rel=1e-8, resid=1e-8, nev=20, proj=1e-6)
+    O2 = oracle_pencil("three_layer_planet", n_half=4, order=2, pres_order=1)
+    for (a, b), r in zip(reqs[1][1], mix[1]["slices"]):
+        w, X = window_ref("three_layer_planet", a, b, n_half=4, order=2, pres_order=1)
+        check_against_oracle(r, w, X, O2.M, rel=1e-9, resid=1e-8)
 
 
 def test_server_budget_serialises_and_rotation():

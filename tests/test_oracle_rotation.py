@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from conftest import pencil
+from conftest import pencil, planet
 from oracle import rotation as RT
 from oracle import solve as S
 from oracle.assemble import Pencil, omega_cross
@@ -71,3 +71,56 @@ def test_projection_matches_first_order_at_small_rate():
         errs.append(np.abs(got - ref).max())
     assert errs[1] < errs[0] / 3.0
     assert errs[0] < 0.01 * 0.02
+
+
+def _small_ball(om):
+    d = dict(planet("homogeneous_ball", n_half=3, order=1))
+    d["omega"] = om
+    P = Pencil(d)
+    return P, P.AG.toarray(), P.M.toarray(), P.R.toarray()
+
+
+def test_exact_qep_without_rotation_is_sqrt_lambda():
+    """R = 0: the QEP's positive frequencies are the square roots of the
+    pencil's eigenvalues in the window, and every companion eigenvalue is real."""
+    P, A, M, R = _small_ball((0.0, 0.0, 0.0))
+    w, U = RT.qep_exact(A, M, R, 4.0, 40.0)
+    lam, _ = S.dense_window(A, M, 4.0, 40.0)
+    assert len(w) == len(lam) > 10
+    assert np.abs(w - np.sqrt(lam)).max() <= 1e-10 * w.max()
+    assert RT.qep_residual(A, M, R, w, U).max() < 1e-10
+
+
+def test_exact_qep_real_spectrum_and_first_order_splitting():
+    """Gyroscopic QEP (A semidefinite, R skew): the companion spectrum is real
+    and modes solve the QEP with orthonormality eq. "orthonormalcond".  Near
+    an isolated cluster the exact frequencies approach the degenerate
+    first-order theory, eig(diag(sqrt lambda) + i U^T R U), with an error that
+    falls ~4x when Omega halves (second order in Omega)."""
+    errs = []
+    for oz in (0.08, 0.04):
+        P, A, M, R = _small_ball((0.0, 0.0, oz))
+        n = A.shape[0]
+        L = np.block([[np.zeros((n, n)), np.eye(n)], [np.linalg.solve(M, A), 2j * np.linalg.solve(M, R)]])
+        ev = np.linalg.eigvals(L)
+        assert np.abs(ev.imag).max() <= 1e-8 * np.abs(ev).max()
+        lam, X = S.dense_window(A, M, 0.5, 80.0)
+        # the lowest toroidal-like cluster: the first eigenvalue group well separated from the next
+        gaps = np.diff(lam)
+        i0 = 0
+        j = i0 + 1
+        while j < len(lam) and gaps[j - 1] < 0.03 * lam[j]:
+            j += 1
+        cl = slice(i0, j)
+        lo, hi = lam[cl].min(), lam[cl].max()
+        w, U = RT.qep_exact(A, M, R, 0.97 * lo, 1.03 * hi)
+        Xc = X[:, cl]
+        Sc = Xc.T @ (R @ Xc)
+        Heff = np.diag(np.sqrt(lam[cl])) + 1j * 0.5 * (Sc - Sc.T)
+        pred = np.sort(np.linalg.eigvalsh(Heff))
+        assert len(w) == len(pred) >= 3
+        assert RT.qep_residual(A, M, R, w, U).max() < 1e-9
+        G = U.conj().T @ (M @ U) - 2j * (U.conj().T @ (R @ U)) / (w[:, None] + w[None, :])
+        assert np.abs(G - np.eye(len(w))).max() < 1e-8
+        errs.append(np.abs(w - pred).max())
+    assert 3.0 < errs[0] / errs[1] < 5.5, errs
