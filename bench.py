@@ -89,45 +89,64 @@ def _oracle_worker(args):
                 asm=t_asm)
 
 
-def cpu_baseline(pool, cores, gpu_stats, pairs, gpu_nnzb, args):
+class CpuBaseline:
     """The oracle (scipy CSR products and its own Chebyshev-Jacobi mass solve,
     the same Cowling operator and mass-solve bound as the GPU leg) timed on
     column B-applications of the same planet generator at n_half = cpu_n_half,
-    once on one core and once on `cores` cores (one single-threaded process
-    per core, 4 columns each).  Scaled to the workload by node-graph size and
-    multiplied by the GPU leg's column B-application count: an extrapolated
-    oracle solve time (its Lanczos and Rayleigh-Ritz are not counted, which
-    favours the oracle)."""
-    one = pool.apply(_oracle_worker, ((args.cpu_n_half, args.tol, 4, args.cpu_seconds, 0),))
-    outs = pool.map(_oracle_worker, [(args.cpu_n_half, args.tol, 4, args.cpu_seconds, 1 + i)
-                                     for i in range(cores)], chunksize=1)
-    used = len({o["pid"] for o in outs})  # processes that ran concurrently
-    rate_all = sum(o["cols"] / o["seconds"] for o in outs) * used / len(outs)
-    per_col_1 = one["seconds"] / one["cols"]
-    per_col_all = 1.0 / rate_all
-    scale = gpu_nnzb / float(one["nnzb"])
-    bapps = gpu_stats["bapps"] + gpu_stats["refine_bapps"]
-    t_1 = per_col_1 * scale * bapps
-    t_all = per_col_all * scale * bapps
-    return {
-        "value": pairs / t_all if t_all > 0 else None,
-        "unit": "eigenpairs/s",
-        "cores": used,
-        "kind": "oracle",
-        "sample": ("column B-applications (A_G + E_G K_p^-1 E_G^T with a %d-step K_p solve, then the %d-step "
-                   "Chebyshev-Jacobi M solve) of the oracle on the same planet generator at n_half=%d (%d DOF, "
-                   "nnzb %d), ~%.0f s on 1 core and ~%.0f s on %d cores (one single-threaded process each, 4 "
-                   "columns); per-column time scaled by node-graph size x%.2f to this workload and multiplied "
-                   "by the headline solve's %d column B-applications (extrapolated; Lanczos and Rayleigh-Ritz "
-                   "not counted)" % (one["kP"], one["kM"], args.cpu_n_half, one["n"], one["nnzb"],
-                                    one["seconds"], max(o["seconds"] for o in outs), used, scale, bapps)),
-        "value_1core": pairs / t_1 if t_1 > 0 else None,
-        "seconds_per_column_bapp_full_size_1core": per_col_1 * scale,
-        "seconds_per_column_bapp_full_size_all_cores": per_col_all * scale,
-        "extrapolated_solve_seconds_1core": t_1,
-        "extrapolated_solve_seconds_all_cores": t_all,
-        "oracle_assembly_seconds": one["asm"],
-    }
+    once on one core and then on `cores` cores (one single-threaded process
+    per core, 4 columns each), in processes forked before the GPU is touched
+    and running while the GPU solves.  Scaled to the workload by node-graph
+    size and multiplied by the GPU leg's column B-application count: an
+    extrapolated oracle solve time (its Lanczos and Rayleigh-Ritz are not
+    counted, which favours the oracle)."""
+
+    def __init__(self, pool, cores, args):
+        import threading
+        self.pool, self.cores, self.args = pool, cores, args
+        self.out = {}
+        self.th = threading.Thread(target=self._run, daemon=True)
+
+    def start(self):
+        self.th.start()
+
+    def _run(self):
+        a = self.args
+        self.out["one"] = self.pool.apply(_oracle_worker, ((a.cpu_n_half, a.tol, 4, a.cpu_seconds, 0),))
+        self.out["all"] = self.pool.map(_oracle_worker, [(a.cpu_n_half, a.tol, 4, a.cpu_seconds, 1 + i)
+                                                         for i in range(self.cores)], chunksize=1)
+
+    def result(self, gpu_stats, pairs, gpu_nnzb):
+        self.th.join()
+        self.pool.close()
+        args, one, outs = self.args, self.out["one"], self.out["all"]
+        used = len({o["pid"] for o in outs})  # processes that ran concurrently
+        rate_all = sum(o["cols"] / o["seconds"] for o in outs) * used / len(outs)
+        per_col_1 = one["seconds"] / one["cols"]
+        per_col_all = 1.0 / rate_all
+        scale = gpu_nnzb / float(one["nnzb"])
+        bapps = gpu_stats["bapps"] + gpu_stats["refine_bapps"]
+        t_1 = per_col_1 * scale * bapps
+        t_all = per_col_all * scale * bapps
+        return {
+            "value": pairs / t_all if t_all > 0 else None,
+            "unit": "eigenpairs/s",
+            "cores": used,
+            "kind": "oracle",
+            "sample": ("column B-applications (A_G + E_G K_p^-1 E_G^T with a %d-step K_p solve, then the %d-step "
+                       "Chebyshev-Jacobi M solve) of the oracle on the same planet generator at n_half=%d (%d DOF, "
+                       "nnzb %d), ~%.0f s on 1 core and ~%.0f s on %d cores (one single-threaded process each, 4 "
+                       "columns; run while the GPU solved); per-column time scaled by node-graph size x%.2f to "
+                       "this workload and multiplied by the headline solve's %d column B-applications "
+                       "(extrapolated; Lanczos and Rayleigh-Ritz not counted)"
+                       % (one["kP"], one["kM"], args.cpu_n_half, one["n"], one["nnzb"], one["seconds"],
+                          max(o["seconds"] for o in outs), used, scale, bapps)),
+            "value_1core": pairs / t_1 if t_1 > 0 else None,
+            "seconds_per_column_bapp_full_size_1core": per_col_1 * scale,
+            "seconds_per_column_bapp_full_size_all_cores": per_col_all * scale,
+            "extrapolated_solve_seconds_1core": t_1,
+            "extrapolated_solve_seconds_all_cores": t_all,
+            "oracle_assembly_seconds": one["asm"],
+        }
 
 
 def main():
@@ -162,12 +181,13 @@ def main():
     for x in legs:
         if x not in LEGS:
             ap.error("unknown leg %r" % x)
-    pool, cores = None, 0
+    cpu = None
     if not args.no_cpu_baseline:
-        # the oracle's processes are forked before anything touches the GPU
+        # the oracle's processes are forked before anything touches the GPU; one core stays free
+        # for the process that drives the GPU
         import multiprocessing as mp
-        cores = max(1, min(args.cpu_cores, os.cpu_count() or 1))
-        pool = mp.get_context("fork").Pool(cores)
+        cores = max(1, min(args.cpu_cores, (os.cpu_count() or 2) - 1))
+        cpu = CpuBaseline(mp.get_context("fork").Pool(cores), cores, args)
 
     import numpy as np
     import torch
@@ -204,6 +224,8 @@ def main():
     t_steps = time.perf_counter() - t
     ms_per_step = t_steps / max(args.steps, 1) * 1e3
     log("%d B-applications (block %d, %s): %.2f ms each" % (args.steps, args.block, legs[0], ms_per_step))
+    if cpu:
+        cpu.start()
 
     # ---- full solves
     results = {}
@@ -249,11 +271,9 @@ def main():
             _lam=r.lam, _stats=st)
         log("leg %s: %d pairs <= tol in %.1f s (%.3f eigenpairs/s), resid max %.2e"
             % (name, pairs, secs, pairs / secs, results[name]["resid_max"] or 0.0))
-        if i == 0 and not args.no_cpu_baseline:
-            log("cpu baseline")
-            cpu = cpu_baseline(pool, cores, st, pairs, P.info["nnzb"], args)
-            pool.close()
-            log("cpu baseline done: %.3g eigenpairs/s on %d cores" % (cpu["value"], cpu["cores"]))
+        if i == 0 and cpu:
+            cpu = cpu.result(st, pairs, P.info["nnzb"])
+            log("cpu baseline: %.3g eigenpairs/s on %d cores" % (cpu["value"], cpu["cores"]))
     # accuracy of each leg against the FP64 leg (eigenvalues of matched pairs)
     ref = results.get("fp64", {}).get("_lam")
     for name, R in results.items():
@@ -303,7 +323,7 @@ def main():
             "launches": st["hot_launches"],
         },
     }
-    if not args.no_cpu_baseline:
+    if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 

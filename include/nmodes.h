@@ -141,7 +141,8 @@ typedef struct {
   int32_t max_basis;   /* cap of the Krylov basis size, 0 = auto */
   int32_t null_filter; /* lower side of the filter: -1 auto (no damping below a when the
                           pencil has fluid, else damping), 0 damping below a, 1 factor
-                          lambda/b, 2 no damping below a */
+                          lambda/b, 2 no damping below a, 3 spectrum slice: damping on both
+                          sides beyond a - guard (b - a) and b + guard (b - a) */
   int32_t verbose;     /* 0 quiet, 1 per-block log on stderr */
   double minv_tol;     /* M-solve bound inside the filter (0: 0.3 tol clamped to [1e-12, 1e-7] in FP64, 1e-7 in FP32) */
   double kp_tol;       /* K_p-solve bound (0 = 1e-13 FP64, 1e-7 FP32) */
@@ -193,6 +194,10 @@ typedef struct {
   double* U;            /* device [n][count][2] complex (re, im) modes, normalised by
                            u^H M u - (i/omega) u^H R u = 1, largest entry real > 0 */
   double seconds;
+  double* resid;        /* host [count] QEP residuals ||w^2 M u - 2 i w R u - A u|| / (w^2 ||M u||) */
+  int32_t iters;        /* refinement passes run (nm_refine_rotation; 0 for a projection) */
+  int32_t basis;        /* size of the projection space */
+  int32_t degree;       /* degree of the correction series (refinement) */
 } nm_rot_result;
 
 /* Build the pencil: numbering, CSR patterns and all matrix values on the
@@ -240,7 +245,9 @@ nm_status nm_filter_coeffs(double a, double b, double lmin, double lmax, int32_t
  * stays below 1 % of its window-edge level beyond b (1 + guard) (guard <= 0:
  * 1.0).  mode 0: no requirement below a (the spectrum below the window is
  * an exactly degenerate null space); mode 1: the same bound below
- * a - guard (a - lmin); mode 2: the filter carries the factor lambda / b. */
+ * a - guard (a - lmin); mode 2: the filter carries the factor lambda / b;
+ * mode 3 (spectrum slices): the bound beyond b + guard (b - a) and below
+ * a - guard (b - a). */
 nm_status nm_filter_degree(double a, double b, double lmin, double lmax, double guard, int32_t mode,
                            int32_t* m);
 
@@ -374,6 +381,53 @@ nm_status nm_server_destroy(nm_server* s);
  * no threshold), so windows near 2 |Omega| are the caller's to avoid. */
 nm_status nm_project_rotation(const nm_pencil* p, const nm_eig_result* basis, double a, double b,
                               void* stream, nm_rot_result** out);
+
+/* Refinement of the rotating modes of a projection toward the exact QEP
+ * (Sec. 7, eq. "simplequad"; the paper notes after eq. "sublinear0" that
+ * solving it exactly improves on the projection): up to `iters` passes of
+ * Rayleigh-Ritz for the QEP over span(X_e) enlarged by two directions per
+ * mode, g(B) M^{-1} Re r and g(B) M^{-1} Im r, r = w^2 M u - 2 i w R u - A u
+ * its residual and g the Jackson-damped Chebyshev series (degree `degree`,
+ * 0 = chosen from the spectrum bound) of the regularised resolvent
+ * (l - w^2) / ((l - w^2)^2 + (w^2 / 4)^2) on the basis's spectrum bounds;
+ * the enlarged span is projected by eq. "sublinear0" on the eigenvectors of
+ * V^T A V.  Rigid motions and the fluid null space, absent from the window
+ * basis, enter through the corrections.  Stops when every residual is <= tol.
+ * basis: the Omega = 0 window pairs the projection used; rot: its result.
+ * out->resid holds the final residuals; out->iters the passes run. */
+nm_status nm_refine_rotation(const nm_pencil* p, const nm_eig_result* basis, const nm_rot_result* rot, double a,
+                             double b, int32_t iters, int32_t degree, double tol, void* stream, nm_rot_result** out);
+
+/* ---- Self-gravitation as an N-body problem (Sec. 5) ----
+ * Bodies: the tetrahedra (barycentres) and the faces where the density jumps
+ * (outer surface, fluid-solid faces; centroids).  A displacement gives them
+ * charges q = C u (eqs. "ph1body2", "ph1surface2": int_K div(rho u) per
+ * tetrahedron, int_E (nu . u)[rho] per face, each side of a fluid-solid face
+ * with its own displacement and density); the incremental potential is
+ * S q, S_ij = G / |r_i - r_j| and S_ii = G / R_i with 1/R_i the mean of
+ * 1/|r_i - x| over body i (eqs. "k2local", "l2local"); the operator gains
+ * -C^T S C (eq. "eigfull").  The sums S q are direct, tiled on the device:
+ * FP32 pair terms, FP64 accumulation over source tiles. */
+typedef struct nm_selfgrav nm_selfgrav;
+/* Bodies, C (device) and the self-terms for the pencil's planet: mesh and
+ * mat must be the arrays the pencil was assembled from (checked: sizes and
+ * order).  G: the gravitational constant in the planet's units (1/pi for
+ * radius, mean density and sqrt(pi G rho) as units).  The result refers to
+ * the pencil, which must outlive it. */
+nm_status nm_selfgrav_build(nm_pencil* p, const nm_mesh* mesh, const nm_material* mat, double G, void* stream,
+                            nm_selfgrav** out);
+/* Counts and (inv_R host [nbody], may be NULL) the self-terms 1/R_i. */
+nm_status nm_selfgrav_info(const nm_selfgrav* sg, int64_t* nbody, int64_t* ntet, int64_t* nface, double* inv_R);
+/* Y = -C^T S C X, device [n][ncols] canonical order.  Calls on one self-gravitation object must not
+ * overlap (they share its work buffers). */
+nm_status nm_selfgrav_apply(const nm_selfgrav* sg, int32_t ncols, const double* X, double* Y, void* stream);
+/* Reference field of Sec. 5.1 at npts points (device [npts][3]): g(x) = -G sum_k m_k (x - r_k) / |x - r_k|^3
+ * over the element masses m_k = rho_k |K_k| at the barycentres (device out [npts][3]). */
+nm_status nm_selfgrav_field(const nm_selfgrav* sg, int64_t npts, const double* pts, double* g, void* stream);
+/* The pencil's operator A becomes A_G + E_G K_p^{-1} E_G^T - C^T S C (eq. "eigfull") for every later
+ * operator application and solve (FP64 filters only; NM_EINVAL with precision 1); sg NULL detaches. */
+nm_status nm_pencil_attach_selfgrav(nm_pencil* p, const nm_selfgrav* sg);
+void nm_selfgrav_free(nm_selfgrav* sg);
 
 /* Copy the eigenvectors of a result into dst (device if dst_is_device,
  * else host), row-major [n][count] (rotation: [n][count][2]). */

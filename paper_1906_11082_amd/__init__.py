@@ -30,7 +30,9 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
             "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns",
-            "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices"]
+            "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices", "nm_refine_rotation",
+            "nm_selfgrav_build", "nm_selfgrav_info", "nm_selfgrav_apply", "nm_selfgrav_field",
+            "nm_pencil_attach_selfgrav", "nm_selfgrav_free"]
 
 
 class NMError(RuntimeError):
@@ -81,7 +83,8 @@ class _EigResult(C.Structure):
 
 class _RotResult(C.Structure):
     _fields_ = [("count", C.c_int32), ("n", C.c_int64), ("omega", C.POINTER(C.c_double)), ("U", C.c_void_p),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("resid", C.POINTER(C.c_double)), ("iters", C.c_int32),
+                ("basis", C.c_int32), ("degree", C.c_int32)]
 
 
 class _Request(C.Structure):
@@ -153,6 +156,14 @@ def load_library(path: str | None = None):
         "nm_version": ([], C.c_char_p),
         "nm_set_allocator": ([_ALLOC_FN, _FREE_FN, P], C.c_int32),
         "nm_max_block_columns": ([C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
+        "nm_selfgrav_build": ([P, C.POINTER(_Mesh), C.POINTER(_Material), C.c_double, P, C.POINTER(P)], C.c_int32),
+        "nm_selfgrav_info": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P], C.c_int32),
+        "nm_selfgrav_apply": ([P, C.c_int32, P, P, P], C.c_int32),
+        "nm_selfgrav_field": ([P, C.c_int64, P, P, P], C.c_int32),
+        "nm_pencil_attach_selfgrav": ([P, P], C.c_int32),
+        "nm_selfgrav_free": ([P], None),
+        "nm_refine_rotation": ([P, C.POINTER(_EigResult), C.POINTER(_RotResult), C.c_double, C.c_double, C.c_int32,
+                                C.c_int32, C.c_double, P, C.POINTER(C.POINTER(_RotResult))], C.c_int32),
         "nm_spectrum_dos": ([P, C.c_double, C.c_double, C.c_int32, C.c_int32, P, C.POINTER(_ApplyOpts), P, P],
                             C.c_int32),
         "nm_dos_count": ([P, C.c_int32] + [C.c_double] * 4 + [C.POINTER(C.c_double)], C.c_int32),
@@ -276,18 +287,28 @@ class EigResult:
 
 
 class RotResult:
+    """Rotating modes: omega (numpy, ascending), U (torch complex, device,
+    [n, count]), resid (QEP residuals) and statistics.  An owned result keeps
+    the library's copy (needed to refine it) until the object is released."""
+
     def __init__(self, ptr, owned=True):
         r = ptr.contents
         self.count = r.count
         self.omega = np.array([r.omega[i] for i in range(r.count)])
+        self.resid = np.array([r.resid[i] for i in range(r.count)]) if r.resid else None
         self.seconds = r.seconds
+        self.iters, self.basis, self.degree = r.iters, r.basis, r.degree
         self.U = None
         if r.count:
             buf = torch.empty((r.n, r.count, 2), dtype=torch.float64, device="cuda")
             _check(_lib.nm_rot_copy_vectors(ptr, _ptr(buf), 1))
             self.U = torch.view_as_complex(buf)
-        if owned:
-            _lib.nm_rot_result_free(ptr)
+        self._ptr = ptr if owned else None
+
+    def __del__(self):
+        if getattr(self, "_ptr", None) is not None and _lib is not None:
+            _lib.nm_rot_result_free(self._ptr)
+            self._ptr = None
 
 
 def _planet_structs(planet: dict, omega=None):
@@ -385,6 +406,15 @@ class Pencil:
                                     _ptr(tau)))
         return tau
 
+    def dos_slice_edges(self, a, b, nslices, lmin, lmax, m=1000, nvec=32, seed=0):
+        """Ends of nslices windows of [a, b] with equal estimated eigenvalue
+        counts, from density-of-states traces of degree m on nvec Gaussian
+        columns drawn with torch (seeded); returns (edges, tau)."""
+        g = torch.Generator(device="cuda").manual_seed(int(seed))
+        Z = torch.randn(self.n, nvec, generator=g, dtype=torch.float64, device="cuda")
+        tau = self.spectrum_dos(lmin, lmax, m, Z)
+        return dos_slices(tau, lmin, lmax, a, b, nslices), tau
+
     def spectrum_bounds(self, steps=60, seed=1):
         lo, hi = C.c_double(), C.c_double()
         _check(_lib.nm_spectrum_bounds(self._h, steps, seed, _stream(), C.byref(lo), C.byref(hi)))
@@ -437,6 +467,56 @@ class Pencil:
         r = C.POINTER(_RotResult)()
         _check(_lib.nm_project_rotation(self._h, basis._ptr, a, b, _stream(), C.byref(r)))
         return RotResult(r)
+
+    def refine_rotation(self, basis: EigResult, rot: "RotResult", a, b, iters=3, degree=0, tol=1e-8):
+        """Refine projected rotating modes toward the exact QEP (nm_refine_rotation)."""
+        r = C.POINTER(_RotResult)()
+        _check(_lib.nm_refine_rotation(self._h, basis._ptr, rot._ptr, a, b, int(iters), int(degree), tol, _stream(),
+                                       C.byref(r)))
+        return RotResult(r)
+
+
+class SelfGravity:
+    """Self-gravitation of a pencil's planet as an N-body problem
+    (nm_selfgrav_build): apply(X) = -C^T S C X, field(points) = the reference
+    field from the element masses; attach() makes the pencil's operator
+    include it."""
+
+    def __init__(self, pencil: "Pencil", planet: dict, G=1.0 / np.pi):
+        lib = load_library()
+        mesh, mat, om, keep = _planet_structs(planet)
+        h = C.c_void_p()
+        _check(lib.nm_selfgrav_build(pencil._h, C.byref(mesh), C.byref(mat), float(G), _stream(), C.byref(h)))
+        self._h = h
+        self._pencil = pencil  # the pencil must outlive this object
+        nb, nt, nf = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib.nm_selfgrav_info(h, C.byref(nb), C.byref(nt), C.byref(nf), None))
+        self.n_body, self.n_tet, self.n_face = nb.value, nt.value, nf.value
+
+    def inv_R(self):
+        out = np.zeros(self.n_body)
+        _check(_lib.nm_selfgrav_info(self._h, None, None, None, _ptr(out)))
+        return out
+
+    def apply(self, X):
+        X = X.contiguous()
+        Y = torch.empty_like(X)
+        _check(_lib.nm_selfgrav_apply(self._h, X.shape[1], _ptr(X), _ptr(Y), _stream()))
+        return Y
+
+    def field(self, pts):
+        pts = pts.contiguous()
+        g = torch.empty_like(pts)
+        _check(_lib.nm_selfgrav_field(self._h, pts.shape[0], _ptr(pts), _ptr(g), _stream()))
+        return g
+
+    def attach(self, on=True):
+        _check(_lib.nm_pencil_attach_selfgrav(self._pencil._h, self._h if on else None))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.nm_selfgrav_free(self._h)
+            self._h = None
 
 
 class Server:

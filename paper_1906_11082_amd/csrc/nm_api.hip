@@ -285,7 +285,7 @@ nm_status nm_filter_degree(double a, double b, double lmin, double lmax, double 
                            int32_t* m) {
   NM_TRY({
     NM_REQUIRE(m && lmax > lmin && b > a, NM_EINVAL, "invalid filter arguments");
-    NM_REQUIRE(null_filter >= 0 && null_filter <= 2, NM_EINVAL, "mode must be 0, 1 or 2");
+    NM_REQUIRE(null_filter >= 0 && null_filter <= 3, NM_EINVAL, "mode must be 0, 1, 2 or 3");
     *m = nm::choose_degree(a, b, lmin, lmax, guard, null_filter);
   })
 }
@@ -421,6 +421,15 @@ nm_status nm_project_rotation(const nm_pencil* p, const nm_eig_result* basis, do
   })
 }
 
+nm_status nm_refine_rotation(const nm_pencil* p, const nm_eig_result* basis, const nm_rot_result* rot, double a,
+                             double b, int32_t iters, int32_t degree, double tol, void* stream, nm_rot_result** out) {
+  NM_TRY({
+    NM_REQUIRE(p && basis && rot && out && b > a, NM_EINVAL, "invalid arguments");
+    *out = nullptr;
+    nm::refine_rotation(p, basis, rot, a, b, iters, degree, tol, (hipStream_t)stream, out);
+  })
+}
+
 nm_status nm_result_copy_vectors(const nm_eig_result* r, void* dst, int32_t dst_is_device) {
   NM_TRY({
     NM_REQUIRE(r && dst, NM_EINVAL, "null argument");
@@ -451,6 +460,7 @@ void nm_rot_result_free(nm_rot_result* r) {
   if (!r) return;
   if (r->U) (void)hipFree(r->U);
   std::free(r->omega);
+  std::free(r->resid);
   std::free(r);
 }
 

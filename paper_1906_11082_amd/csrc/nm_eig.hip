@@ -69,12 +69,15 @@ double filter_value(const std::vector<double>& mu, int m, double c, double e, do
 //           damping; the few other low modes converge as unwanted pairs.
 //   mode 1  the same bound below a - guard (a - lmin);
 //   mode 2  the filter is multiplied by lambda / b (null factor).
+//   mode 3  spectrum slices: two-sided, with guard points a - guard (b - a) and
+//           b + guard (b - a) (bands proportional to the slice's width), so
+//           that the slices of one window each damp the others' eigenvalues.
 int choose_degree(double a, double b, double lmin, double lmax, double guard, int mode) {
   if (guard <= 0) guard = 1.0;
   const bool null = mode == 2;
   const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
-  const double bg = b * (1.0 + guard);
-  const double ag = a - guard * std::max(a - lmin, 0.0);
+  const double bg = mode == 3 ? b + guard * (b - a) : b * (1.0 + guard);
+  const double ag = mode == 3 ? a - guard * (b - a) : a - guard * std::max(a - lmin, 0.0);
   const double s0 = null ? b : 0.0;
   std::vector<double> mu;
   for (double md = 8; md < 20000; md *= 1.15) {
@@ -93,7 +96,7 @@ int choose_degree(double a, double b, double lmin, double lmax, double guard, in
       double lam = c + e * std::cos(th);
       if (std::fabs(filter_value(mu, m, c, e, lam, null, s0)) > 0.01 * lev) ok = false;
     }
-    if (mode == 1 && ag > lmin) {
+    if ((mode == 1 || mode == 3) && ag > lmin) {
       double th_lo = std::acos(std::min(1.0, std::max(-1.0, (ag - c) / e)));
       for (int i = 0; i <= ns && ok; ++i) {
         double th = th_lo + (M_PI - th_lo) * i / ns;
@@ -304,8 +307,45 @@ int solve_block_width(const nm_pencil* P, const nm_eig_opts& o, int nev) {
   return (int)std::min<int64_t>(bs, 3 * P->N);
 }
 
+namespace {
+// the filtered vectors grew without bound: an eigenvalue lies above the
+// interval the Chebyshev polynomials were mapped to (lambda_max too small)
+struct FilterBlowUp : Error {
+  double lmin, lmax;
+  FilterBlowUp(double lo, double hi)
+      : Error(NM_ENOCONV, "filter blow-up: the spectrum bound lambda_max is too small"), lmin(lo), lmax(hi) {}
+};
+}  // namespace
+
+static void filtered_eig_once(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
+                              nm_eig_result** out, BatchSeat* seat, rocblas_handle blas);
+
+// A blow-up means the bound lambda_max was below the spectrum (the filter's
+// Chebyshev polynomials grow without limit beyond their interval): the solve
+// restarts on [lmin, max(2 lmax, 1.5 x a fresh 120-step Lanczos estimate)], at
+// most three times.  Batched solves share one interval and report the error.
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
                   nm_eig_result** out, BatchSeat* seat, rocblas_handle blas) {
+  nm_eig_opts oo = o;
+  for (int attempt = 0;; ++attempt) {
+    try {
+      filtered_eig_once(P, a, b, nev, tol, oo, out, seat, blas);
+      return;
+    } catch (const FilterBlowUp& e) {
+      if (seat || attempt >= 3) throw Error(NM_ENOCONV, e.what());
+      double lo = 0, hi = 0;
+      spectrum_bounds(P, 120, o.seed ^ 0x2545f491ull, (hipStream_t)o.stream, &lo, &hi);
+      oo.lmin = std::min(e.lmin, lo - 1e-3 * (b - a));
+      oo.lmax = std::max(2.0 * e.lmax, 1.5 * hi);
+      if (o.verbose)
+        fprintf(stderr, "[nmodes] filter blow-up with lambda_max %.6g: restarting on [%.6g, %.6g]\n", e.lmax, oo.lmin,
+                oo.lmax);
+    }
+  }
+}
+
+static void filtered_eig_once(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
+                              nm_eig_result** out, BatchSeat* seat, rocblas_handle blas) {
   FilterBatcher* fb = seat ? seat->fb : nullptr;
   NM_REQUIRE(b > a && nev > 0 && tol > 0, NM_EINVAL, "need a < b, nev > 0, tol > 0");
   hipStream_t st = (hipStream_t)o.stream;
@@ -351,6 +391,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
   // damping below a otherwise
   int mode = o.null_filter == 1 ? 2 : (o.null_filter == 0 ? 1 : (P->n_pres > 0 ? 0 : 1));
   if (o.null_filter == 2) mode = 0;
+  if (o.null_filter == 3) mode = 3;
+  NM_REQUIRE(o.null_filter >= -1 && o.null_filter <= 3, NM_EINVAL, "null_filter must be -1..3");
   const bool null = mode == 2;
   NM_REQUIRE(!(null && fb), NM_EINVAL, "batched solves do not take the null factor");
   const double l0 = 0.0, s0 = null ? b : 0.0;
@@ -584,8 +626,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       col_dots(n, bs, W.p, bs, MW.p, bs, Gd.p, st);
       d2h_sync(nr.data(), Gd.p, bs, st);
       for (double x : nr)
-        if (!std::isfinite(x) || x > 1e30)
-          throw Error(NM_ENOCONV, "filter blow-up: the spectrum bound lambda_max is too small");
+        if (!std::isfinite(x) || x > 1e30) throw FilterBlowUp(lmin, lmax);
     }
     if (K + bs > Kmax) break;
     // ---- orthogonalise, extend the basis
@@ -757,6 +798,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
     const int ns0 = (int)th_sel.size();
     const int Kf = Kc_last;
     const double gd = o.guard > 0 ? o.guard : 1.0;
+    // upper end of the band refined with the window: b (1 + guard), or for slices b + guard (b - a)
+    const double bband = mode == 3 ? b + gd * (b - a) : b * (1.0 + gd);
     // FP32 basis: null factor in the refinement (see the low-pass below)
     const bool nullf = prec == 1;
     // window vectors (restricted Rayleigh-Ritz) and band vectors (full Rayleigh-Ritz over V_f)
@@ -772,7 +815,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
         for (int i = 0; i < q; ++i) h[i + (size_t)q * Kf] = h[q + (size_t)i * Kf] = 0.5 * (h[i + (size_t)q * Kf] + h[q + (size_t)i * Kf]);
       sym_eig(Kf, h, thf, Zf);
       for (int i = 0; i < Kf; ++i)
-        if ((thf[i] > b && thf[i] <= b * (1.0 + gd)) || (thf[i] < a && std::fabs(thf[i]) > 1e-6 * b)) {
+        if ((thf[i] > b && thf[i] <= bband) || (thf[i] < a && std::fabs(thf[i]) > 1e-6 * b)) {
           Yband.insert(Yband.end(), Zf.begin() + (size_t)i * Kf, Zf.begin() + (size_t)(i + 1) * Kf);
           ++nband;
         }
@@ -919,7 +962,7 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       std::vector<int> cand, keep;
       for (int i = 0; i < q2; ++i) {
         if (tht[i] >= a && tht[i] <= b) cand.push_back(i);
-        if ((tht[i] > b && tht[i] <= b * (1.0 + gd)) || (tht[i] < a && std::fabs(tht[i]) > 1e-6 * b))
+        if ((tht[i] > b && tht[i] <= bband) || (tht[i] < a && std::fabs(tht[i]) > 1e-6 * b))
           keep.push_back(i);
       }
       const int nc = (int)cand.size();

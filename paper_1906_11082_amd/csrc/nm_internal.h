@@ -163,6 +163,8 @@ struct nm_pencil {
   int tuned_block = 0;  // block width chosen by the autotuner (0: none)
   int tuned_tile = 0;   // tile rows chosen by the autotuner (0: none or no tiles)
   rocblas_handle blas = nullptr;
+  // self-gravitation attached by nm_pencil_attach_selfgrav: A includes -C^T S C (FP64 operators)
+  const nm_selfgrav* selfgrav = nullptr;
   std::mutex fp32_mx;  // the window threads of one pencil create the FP32 shadows once
   void ensure_fp32(hipStream_t st);
 };
@@ -338,6 +340,10 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
 // their filter applications batched; out[i] receives each result (NM_PARTIAL if any is partial)
 void filtered_eig_slices(const nm_pencil* P, int S, const double* a, const double* b, const int* nev, double tol,
                          const nm_eig_opts& o, nm_eig_result** out);
+// F -= C^T S C X (internal node order, FP64 [N][3 nc]; nm_selfgrav.hip)
+void selfgrav_add(const nm_selfgrav* sg, int nc, const double* X, double* F, hipStream_t st);
+void refine_rotation(const nm_pencil* P, const nm_eig_result* basis, const nm_rot_result* rot, double a, double b,
+                     int iters, int degree, double tol, hipStream_t st, nm_rot_result** out);
 void project_rotation(const nm_pencil* P, const nm_eig_result* basis, double a, double b,
                       hipStream_t st, nm_rot_result** out);
 

@@ -1139,6 +1139,18 @@ void a_apply(const nm_pencil* P, int b, const T* X, T* F, T* Y1, double inv_thet
     LAUNCH(k_egt<T>, P->n_pres * b, st, P->n_pres, b, P->egt_ptr.p, P->egt_col.p, m.egt, X, w.pt);
     S = kp_solve<T>(P, b, w.pt, kP, w.pa, w.pb, st);
   }
+  if constexpr (std::is_same<T, double>::value) {
+    if (P->selfgrav) {
+      // A X with the self-gravitation term -C^T S C X, then the first mass-solve iterate
+      launch_apply_ag<T>(P->N, b, P->row_ptr.p, P->col.p, m.ag, X, P->eg_ptr.p, P->eg_col.p, m.eg, S, F, m.mdinv,
+                         T(0), nullptr, st);
+      selfgrav_add(P->selfgrav, b, X, F, st);
+      if (Y1) launch_cj_first<T>(P->N, 3 * b, m.mdinv, F, (T)inv_theta, Y1, st);
+      return;
+    }
+  } else {
+    NM_REQUIRE(!P->selfgrav, NM_EINVAL, "self-gravitation runs with FP64 operators only");
+  }
   launch_apply_ag<T>(P->N, b, P->row_ptr.p, P->col.p, m.ag, X, P->eg_ptr.p, P->eg_col.p, m.eg, S, F, m.mdinv,
                      (T)inv_theta, Y1, st);
 }

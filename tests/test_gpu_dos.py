@@ -1,4 +1,6 @@
 """GPU density of states (kernel polynomial method) against the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -6,12 +8,14 @@ from conftest import planet as make_planet, pencil as oracle_pencil
 
 pytestmark = pytest.mark.gpu
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+
 
 def test_dos_traces_match_oracle():
     """tau_k from the GPU recurrence equal the oracle's for the same random
-    block (1e-9 of the largest, degree 200), and at degree 1200 the count they
-    give for [1, 12] is the oracle window's count within the stochastic error
-    (Hutchinson, 32 vectors) and the kernel's smoothing at the window ends."""
+    block (1e-9 of the largest, degree 200), and the count they give for
+    [1, 12] is the oracle window's count (stored, the same planet) within the
+    estimator's sampling error and the kernel's smoothing at the window ends."""
     import torch
     import paper_1906_11082_amd as nm
     from oracle import dos as D
@@ -30,8 +34,20 @@ def test_dos_traces_match_oracle():
     err = np.abs(tau - ref).max() / np.abs(ref).max()
     print("dos traces: max rel difference %.2e" % err, flush=True)
     assert err <= 1e-9
-    w, _ = S.cowling_window(O, 1.0, 12.0)
-    tau = G.spectrum_dos(lmin, lmax, 1200, Z, minv_tol=1e-12, kp_tol=1e-13)
-    est = nm.dos_count(tau, lmin, lmax, 1.0, 12.0)
-    print("count [1, 12]: estimate %.1f, oracle %d" % (est, len(w)), flush=True)
-    assert abs(est - len(w)) <= 6 * np.sqrt(2 * len(w) / 32) + 3
+    # counts: 8 independent estimates of 16 Gaussian columns each at degree
+    # 3000, where the Jackson kernel's leak from the null cluster at 0 into
+    # [1, 12] is below 1 eigenvalue on this planet (0.8 at degree 2000 and
+    # 0.3 at 3000 with the exact eigenvalues of the dense pencil).  Their mean is the window's count
+    # within its own sampling error (the estimator is unbiased).
+    w = np.loadtxt(os.path.join(HERE, "golden", "cowling_window_nh4.txt"))
+    g = torch.Generator(device="cuda").manual_seed(11)
+    est = []
+    for _ in range(8):
+        Zg = torch.randn(G.n, 16, generator=g, dtype=torch.float64, device="cuda")
+        tau = G.spectrum_dos(lmin, lmax, 3000, Zg, minv_tol=1e-12, kp_tol=1e-13)
+        est.append(nm.dos_count(tau, lmin, lmax, 1.0, 12.0))
+    est = np.array(est)
+    se = est.std(ddof=1) / np.sqrt(len(est))
+    print("count [1, 12] (lmax %.4g): estimates %s, mean %.2f +- %.2f, oracle %d"
+          % (lmax, np.round(est, 1), est.mean(), se, len(w)), flush=True)
+    assert abs(est.mean() - len(w)) <= 4.0 * se + 1.0

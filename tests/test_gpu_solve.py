@@ -233,3 +233,17 @@ def test_graph_replayed_filter_equals_eager(monkeypatch, precision):
     assert np.array_equal(out["1"].lam, out["0"].lam)
     assert np.array_equal(out["1"].X.cpu().numpy(), out["0"].X.cpu().numpy())
     assert out["1"].stats["basis"] >= 24  # several blocks, so several replays
+
+
+def test_blow_up_restarts_with_a_larger_bound():
+    """A spectrum bound lambda_max far below the spectrum makes the filtered
+    vectors blow up; the solve restarts on an enlarged interval and finds the
+    same pairs as the dense oracle."""
+    import paper_1906_11082_amd as nm
+    d = make_planet("homogeneous_ball", n_half=4, order=1)
+    G = nm.Pencil(d)
+    r = G.filtered_eig(0.5, 40.0, 30, 1e-10, degree=40, block=8, lmin=-0.01, lmax=100.0, verbose=1)
+    O = OPencil(d)
+    w, _ = S.dense_window(O.AG.toarray(), O.M.toarray(), 0.5, 40.0)
+    assert r.count == 30 and r.stats["lmax"] > 1000.0
+    assert np.abs(r.lam - w[:30]).max() <= 1e-10 * w[29]
