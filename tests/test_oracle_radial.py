@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def _roots(f, lo, hi, count, n=20000):
     xs = np.linspace(lo, hi, n)
-    v = np.array([f(x) for x in xs])
+    v = f(xs)
     return np.array([so.brentq(f, xs[i], xs[i + 1]) for i in range(n - 1) if v[i] * v[i + 1] < 0][:count])
 
 
