@@ -227,6 +227,24 @@ nm_status nm_pencil_nodes(const nm_pencil* p, int64_t* node_geom, int64_t* pres_
 nm_status nm_pencil_apply(const nm_pencil* p, int32_t op, int32_t ncols, const void* X, void* Y,
                           const nm_apply_opts* opts, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * operators as nm_pencil_apply with every buffer beyond X and Y (the vectors
+ * in the internal node order, the iterates of the inner Chebyshev-Jacobi
+ * solves) in a static device array of NM_NOALLOC_SCRATCH_BYTES per device,
+ * held from library load to process end.  Calls no hipMalloc / hipFree and no
+ * allocating routine, and does not synchronise: Y is complete when the stream
+ * reaches the end of the call.  All calls on one device share the array:
+ * calls that overlap in time on one device (other streams or host threads)
+ * race; calls ordered on one stream do not.  NM_EINVAL: an operator whose
+ * buffers exceed NM_NOALLOC_SCRATCH_BYTES (the message gives the bytes
+ * needed), opts->mass_passes != 0, precision 1 before the pencil's FP32
+ * matrices exist (any allocating FP32 operator or solve creates them), or a
+ * current device other than the pencil's. */
+#define NM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+nm_status nm_pencil_apply_noalloc(const nm_pencil* p, int32_t op, int32_t ncols, const void* X, void* Y,
+                                  const nm_apply_opts* opts, void* stream);
+
 /* Autotuning of the mass-solve step (the hot loop of every filter step) on
  * this pencil: times middle Chebyshev-Jacobi steps for block widths 8, 16,
  * 32 and 64 and, in FP64, the per-row and row-group kernels, then keeps the

@@ -29,7 +29,7 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_filtered_eig_slices", "nm_project_rotation", "nm_pencil_autotune", "nm_server_create",
             "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
-            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns",
+            "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns", "nm_pencil_apply_noalloc",
             "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices", "nm_refine_rotation",
             "nm_selfgrav_build", "nm_selfgrav_info", "nm_selfgrav_apply", "nm_selfgrav_field",
             "nm_pencil_attach_selfgrav", "nm_selfgrav_free"]
@@ -156,6 +156,7 @@ def load_library(path: str | None = None):
         "nm_version": ([], C.c_char_p),
         "nm_set_allocator": ([_ALLOC_FN, _FREE_FN, P], C.c_int32),
         "nm_max_block_columns": ([C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
+        "nm_pencil_apply_noalloc": ([P, C.c_int32, C.c_int32, P, P, C.POINTER(_ApplyOpts), P], C.c_int32),
         "nm_selfgrav_build": ([P, C.POINTER(_Mesh), C.POINTER(_Material), C.c_double, P, C.POINTER(P)], C.c_int32),
         "nm_selfgrav_info": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), P], C.c_int32),
         "nm_selfgrav_apply": ([P, C.c_int32, P, P, P], C.c_int32),
@@ -385,6 +386,14 @@ class Pencil:
         o = self._opts(**kw)
         _check(_lib.nm_pencil_apply(self._h, op, X.shape[1], _ptr(X), _ptr(Y), C.byref(o), _stream()))
         torch.cuda.synchronize()
+        return Y
+
+    def apply_noalloc(self, op, X, Y, **kw):
+        """Y = op(X) through nm_pencil_apply_noalloc into the caller's Y (no
+        device allocation, no synchronisation: Y is ready when torch's current
+        stream reaches this point)."""
+        o = self._opts(**kw)
+        _check(_lib.nm_pencil_apply_noalloc(self._h, op, X.shape[1], _ptr(X), _ptr(Y), C.byref(o), _stream()))
         return Y
 
     def filter_apply(self, mu, c, e, X, null_shift=0.0, null_scale=0.0, **kw):
