@@ -52,6 +52,41 @@ LEGS = {
 }
 
 
+def kernel_fingerprint():
+    """sha256 of the source text of the row-group mass-solve kernel (its
+    gather helper and body), so that HBM traffic measured by rocprofv3 on an
+    earlier build is reported only while the kernel is unchanged."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1906_11082_amd", "csrc", "nm_ops.hip")).read()
+    i = src.index("// sum over the group's union columns")
+    j = src.index("// LDS-tiled Chebyshev-Jacobi step")
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
+
+
+def measured_traffic(kernel, leg, block, n_half):
+    """HBM bytes per launch of the hot kernel from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy's
+    readings), or None if there is none for this kernel, leg and size or the
+    kernel's source has changed since."""
+    path = os.path.join(ROOT, "profiles", "k_cj_group_c2_%s_b%d_traffic.json" % (leg, block))
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if (t.get("kernel") != kernel or t.get("n_half") != n_half or t.get("block") != block
+            or t.get("kernel_source_sha256") != kernel_fingerprint()):
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
+def hot_kernel_name(st, leg):
+    """The template instance of the mass-solve step the leg ran (rows of 3 x 32
+    columns: 4 floats or 2 doubles per lane, 4-row groups)."""
+    if st.get("hot_kernel") != "row-group":
+        return None
+    return "k_cj_group<float, 4, 4>" if leg in ("mixed", "fp32") else "k_cj_group<double, 2, 4>"
+
+
 def log(msg):
     print("[bench %6.1fs] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
 
@@ -315,7 +350,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": hot_gbs / HBM_PEAK_GBS if hot_gbs else None,
-            "traffic": None,
+            "traffic": measured_traffic(hot_kernel_name(st, legs[0]), legs[0], args.block, args.n_half),
             "kernel": "middle Chebyshev-Jacobi step of the mass solve (%s leg)" % legs[0],
             "bytes_per_launch": st["hot_bytes"],
             "mean_launch_ms": st["hot_ms"],

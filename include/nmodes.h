@@ -301,6 +301,23 @@ nm_status nm_dos_count(const double* tau, int32_t m, double lmin, double lmax, d
 nm_status nm_dos_slices(const double* tau, int32_t m, double lmin, double lmax, double a, double b, int32_t nslices,
                         double* edges);
 
+/* Null-free density of states for pencils with a large null space (the
+ * fluid's, exactly degenerate at 0): the same traces with the recurrence
+ * started from B z, tau[k] = (1/nvec) sum_v z_v^T T_k((B - c)/e) B z_v,
+ * estimating tr(T_k(.) B) = sum_i T_k(t_i) lambda_i, in which every
+ * eigenvalue 0 weighs nothing.  Counts then use the Jackson-damped series of
+ * 1/lambda on [a, b] (a > 0), so the kernel's finite resolution cannot leak
+ * the null cluster into a low window (at the benchmark planet's spectrum
+ * width the unweighted kernel smears it over several units of lambda even
+ * at degree 3000).  Arguments as nm_spectrum_dos, nm_dos_count and
+ * nm_dos_slices; NM_EINVAL when a <= 0. */
+nm_status nm_spectrum_dos_weighted(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec,
+                                   const double* Z, const nm_apply_opts* opts, void* stream, double* tau);
+nm_status nm_dos_count_weighted(const double* tau, int32_t m, double lmin, double lmax, double a, double b,
+                                double* count);
+nm_status nm_dos_slices_weighted(const double* tau, int32_t m, double lmin, double lmax, double a, double b,
+                                 int32_t nslices, double* edges);
+
 /* Eigenpairs of the Cowling pencil with a <= omega^2 <= b: the min(nev,
  * count) smallest, by polynomial-filtered block Lanczos in the M-inner
  * product with Rayleigh-Ritz on (A, M) (Sec. 6.1).  tol bounds the
@@ -409,10 +426,15 @@ nm_status nm_project_rotation(const nm_pencil* p, const nm_eig_result* basis, do
  * 0 = chosen from the spectrum bound) of the regularised resolvent
  * (l - w^2) / ((l - w^2)^2 + (w^2 / 4)^2) on the basis's spectrum bounds;
  * the enlarged span is projected by eq. "sublinear0" on the eigenvectors of
- * V^T A V.  Rigid motions and the fluid null space, absent from the window
- * basis, enter through the corrections.  Stops when every residual is <= tol.
+ * V^T A V (all of them: rigid motions and the fluid null space, absent
+ * from the window basis, enter through the corrections; directions of
+ * clearly negative V^T A V are left out).  A pass is kept only if every mode
+ * it returns has a residual below the previous pass's largest (Rayleigh-Ritz
+ * for the QEP can return spurious window values on the enlarged span, seen
+ * on fluid planets); the refinement stops at the first pass that is not, or
+ * when every residual is <= tol.
  * basis: the Omega = 0 window pairs the projection used; rot: its result.
- * out->resid holds the final residuals; out->iters the passes run. */
+ * out->resid holds the final residuals; out->iters the passes kept. */
 nm_status nm_refine_rotation(const nm_pencil* p, const nm_eig_result* basis, const nm_rot_result* rot, double a,
                              double b, int32_t iters, int32_t degree, double tol, void* stream, nm_rot_result** out);
 

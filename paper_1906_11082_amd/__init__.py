@@ -30,7 +30,8 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_server_submit", "nm_server_wait", "nm_server_result_free", "nm_server_destroy",
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
             "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns", "nm_pencil_apply_noalloc",
-            "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices", "nm_refine_rotation",
+            "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices", "nm_spectrum_dos_weighted", "nm_dos_count_weighted",
+            "nm_dos_slices_weighted", "nm_refine_rotation",
             "nm_selfgrav_build", "nm_selfgrav_info", "nm_selfgrav_apply", "nm_selfgrav_field",
             "nm_pencil_attach_selfgrav", "nm_selfgrav_free"]
 
@@ -169,6 +170,10 @@ def load_library(path: str | None = None):
                             C.c_int32),
         "nm_dos_count": ([P, C.c_int32] + [C.c_double] * 4 + [C.POINTER(C.c_double)], C.c_int32),
         "nm_dos_slices": ([P, C.c_int32] + [C.c_double] * 4 + [C.c_int32, P], C.c_int32),
+        "nm_spectrum_dos_weighted": ([P, C.c_double, C.c_double, C.c_int32, C.c_int32, P, C.POINTER(_ApplyOpts), P,
+                                      P], C.c_int32),
+        "nm_dos_count_weighted": ([P, C.c_int32] + [C.c_double] * 4 + [C.POINTER(C.c_double)], C.c_int32),
+        "nm_dos_slices_weighted": ([P, C.c_int32] + [C.c_double] * 4 + [C.c_int32, P], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -224,21 +229,25 @@ def max_block_columns(n_disp):
     return out.value
 
 
-def dos_count(tau, lmin, lmax, a, b):
-    """Estimated eigenvalue count in [a, b] from density-of-states traces (nm_dos_count)."""
+def dos_count(tau, lmin, lmax, a, b, weighted=False):
+    """Estimated eigenvalue count in [a, b] from density-of-states traces
+    (nm_dos_count; weighted: traces of T_k B, nm_dos_count_weighted)."""
     lib = load_library()
     tau = np.ascontiguousarray(tau, np.float64)
     out = C.c_double()
-    _check(lib.nm_dos_count(_ptr(tau), len(tau) - 1, lmin, lmax, a, b, C.byref(out)))
+    fn = lib.nm_dos_count_weighted if weighted else lib.nm_dos_count
+    _check(fn(_ptr(tau), len(tau) - 1, lmin, lmax, a, b, C.byref(out)))
     return out.value
 
 
-def dos_slices(tau, lmin, lmax, a, b, nslices):
-    """Ends of nslices equal-count windows of [a, b] (nm_dos_slices)."""
+def dos_slices(tau, lmin, lmax, a, b, nslices, weighted=False):
+    """Ends of nslices equal-count windows of [a, b] (nm_dos_slices, or
+    nm_dos_slices_weighted for weighted traces)."""
     lib = load_library()
     tau = np.ascontiguousarray(tau, np.float64)
     edges = np.zeros(nslices + 1)
-    _check(lib.nm_dos_slices(_ptr(tau), len(tau) - 1, lmin, lmax, a, b, int(nslices), _ptr(edges)))
+    fn = lib.nm_dos_slices_weighted if weighted else lib.nm_dos_slices
+    _check(fn(_ptr(tau), len(tau) - 1, lmin, lmax, a, b, int(nslices), _ptr(edges)))
     return edges
 
 
@@ -405,24 +414,25 @@ class Pencil:
                                     _ptr(X), _ptr(Y), C.byref(o), _stream()))
         return Y
 
-    def spectrum_dos(self, lmin, lmax, m, Z, **kw):
+    def spectrum_dos(self, lmin, lmax, m, Z, weighted=False, **kw):
         """Density-of-states traces tau[0..m] from the columns of the device
-        block Z [n, nvec] (float64, canonical order; nm_spectrum_dos)."""
+        block Z [n, nvec] (float64, canonical order; nm_spectrum_dos, or
+        nm_spectrum_dos_weighted: traces of T_k B, blind to the null space)."""
         Z = Z.contiguous()
         tau = np.zeros(m + 1)
         o = self._opts(**kw)
-        _check(_lib.nm_spectrum_dos(self._h, lmin, lmax, int(m), Z.shape[1], _ptr(Z), C.byref(o), _stream(),
-                                    _ptr(tau)))
+        fn = _lib.nm_spectrum_dos_weighted if weighted else _lib.nm_spectrum_dos
+        _check(fn(self._h, lmin, lmax, int(m), Z.shape[1], _ptr(Z), C.byref(o), _stream(), _ptr(tau)))
         return tau
 
-    def dos_slice_edges(self, a, b, nslices, lmin, lmax, m=1000, nvec=32, seed=0):
+    def dos_slice_edges(self, a, b, nslices, lmin, lmax, m=1000, nvec=32, seed=0, weighted=False):
         """Ends of nslices windows of [a, b] with equal estimated eigenvalue
         counts, from density-of-states traces of degree m on nvec Gaussian
         columns drawn with torch (seeded); returns (edges, tau)."""
         g = torch.Generator(device="cuda").manual_seed(int(seed))
         Z = torch.randn(self.n, nvec, generator=g, dtype=torch.float64, device="cuda")
-        tau = self.spectrum_dos(lmin, lmax, m, Z)
-        return dos_slices(tau, lmin, lmax, a, b, nslices), tau
+        tau = self.spectrum_dos(lmin, lmax, m, Z, weighted=weighted)
+        return dos_slices(tau, lmin, lmax, a, b, nslices, weighted=weighted), tau
 
     def spectrum_bounds(self, steps=60, seed=1):
         lo, hi = C.c_double(), C.c_double()

@@ -1,8 +1,10 @@
 // C ABI of the library (declared in include/nmodes.h): argument checks,
 // error codes and thread-local messages around the device code.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "nm_internal.h"
 
@@ -319,8 +321,9 @@ nm_status nm_filter_apply(const nm_pencil* p, const double* mu, int32_t m, doubl
   })
 }
 
-nm_status nm_spectrum_dos(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec, const double* Z,
-                          const nm_apply_opts* opts, void* stream, double* tau) {
+static nm_status spectrum_dos_impl(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec,
+                                   const double* Z, const nm_apply_opts* opts, void* stream, double* tau,
+                                   bool weighted) {
   NM_TRY({
     NM_REQUIRE(p && Z && tau && m >= 0 && nvec >= 1 && lmax > lmin, NM_EINVAL, "invalid density-of-states arguments");
     nm::check_block(3 * p->N, nvec);
@@ -330,33 +333,104 @@ nm_status nm_spectrum_dos(const nm_pencil* p, double lmin, double lmax, int32_t 
     const int64_t w = 3 * (int64_t)nvec;
     nm::DBuf<double> zi((size_t)p->N * w);
     nm::permute_rows(p->N, (int)w, Z, zi.p, p->iperm.p, 8, st);
-    nm::dos_traces(p, lmin, lmax, m, nvec, zi.p, cfg, st, tau);
+    nm::dos_traces(p, lmin, lmax, m, nvec, zi.p, cfg, st, tau, weighted);
     NM_HIP(hipGetLastError());
   })
 }
 
-nm_status nm_dos_count(const double* tau, int32_t m, double lmin, double lmax, double a, double b, double* count) {
+nm_status nm_spectrum_dos(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec, const double* Z,
+                          const nm_apply_opts* opts, void* stream, double* tau) {
+  return spectrum_dos_impl(p, lmin, lmax, m, nvec, Z, opts, stream, tau, false);
+}
+
+nm_status nm_spectrum_dos_weighted(const nm_pencil* p, double lmin, double lmax, int32_t m, int32_t nvec,
+                                   const double* Z, const nm_apply_opts* opts, void* stream, double* tau) {
+  return spectrum_dos_impl(p, lmin, lmax, m, nvec, Z, opts, stream, tau, true);
+}
+
+namespace {
+
+// n-point Gauss-Legendre rule on [-1, 1] (Newton on the three-term
+// recurrence of the Legendre polynomials from the usual cosine guesses)
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Jackson-damped Chebyshev coefficients on [lmin, lmax] of f(l) = 1/l on
+// [a, b] (0 elsewhere, a > 0): with l = c + e cos(th),
+// c_k = (2/pi) int over [th_b, th_a] of cos(k th) / (c + e cos th) d th (c_0
+// halved), by 16-point Gauss-Legendre panels short enough for cos(k th)
+void inv_window_coeffs(double a, double b, double lmin, double lmax, int m, double* mu) {
+  const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
+  const double tha = std::acos(std::min(1.0, std::max(-1.0, (a - c) / e)));
+  const double thb = std::acos(std::min(1.0, std::max(-1.0, (b - c) / e)));
+  std::vector<double> gx, gw;
+  gauss_legendre(16, gx, gw);
+  const int panels = std::max(2, (int)std::ceil((m + 1) * (tha - thb) / 2.0) + 2);
+  const double h = (tha - thb) / panels;
+  std::vector<double> acc(m + 1, 0.0);
+  for (int q = 0; q < panels; ++q) {
+    for (int g = 0; g < 16; ++g) {
+      const double th = thb + h * (q + 0.5 * (gx[g] + 1.0));
+      const double wt = 0.5 * h * gw[g] / (c + e * std::cos(th));
+      for (int k = 0; k <= m; ++k) acc[k] += wt * std::cos(k * th);
+    }
+  }
+  const double tj = M_PI / (m + 2);
+  for (int k = 0; k <= m; ++k) {
+    const double jac = ((1.0 - (double)k / (m + 2)) * std::sin(tj) * std::cos(k * tj) +
+                        std::cos(tj) * std::sin(k * tj) / (m + 2)) / std::sin(tj);
+    mu[k] = (k == 0 ? 1.0 : 2.0) / M_PI * acc[k] * jac;
+  }
+}
+
+double dos_estimate(const double* tau, int m, double lmin, double lmax, double a, double b, bool weighted,
+                    std::vector<double>& mu) {
+  mu.resize(m + 1);
+  if (weighted)
+    inv_window_coeffs(a, b, lmin, lmax, m, mu.data());
+  else
+    nm::jackson_chebyshev(a, b, lmin, lmax, m, mu.data());
+  double s = 0;
+  for (int k = 0; k <= m; ++k) s += mu[k] * tau[k];
+  return s;
+}
+
+nm_status dos_count_impl(const double* tau, int32_t m, double lmin, double lmax, double a, double b, double* count,
+                         bool weighted) {
   NM_TRY({
     NM_REQUIRE(tau && count && m >= 0 && lmax > lmin && b > a, NM_EINVAL, "invalid count arguments");
-    std::vector<double> mu(m + 1);
-    nm::jackson_chebyshev(a, b, lmin, lmax, m, mu.data());
-    double s = 0;
-    for (int k = 0; k <= m; ++k) s += mu[k] * tau[k];
-    *count = s;
+    NM_REQUIRE(!weighted || a > 0, NM_EINVAL, "weighted counts need a window above 0");
+    std::vector<double> mu;
+    *count = dos_estimate(tau, m, lmin, lmax, a, b, weighted, mu);
   })
 }
 
-nm_status nm_dos_slices(const double* tau, int32_t m, double lmin, double lmax, double a, double b, int32_t nslices,
-                        double* edges) {
+nm_status dos_slices_impl(const double* tau, int32_t m, double lmin, double lmax, double a, double b,
+                          int32_t nslices, double* edges, bool weighted) {
   NM_TRY({
     NM_REQUIRE(tau && edges && m >= 0 && lmax > lmin && b > a && nslices >= 1, NM_EINVAL, "invalid slice arguments");
-    std::vector<double> mu(m + 1);
-    auto count = [&](double x) {
-      nm::jackson_chebyshev(a, x, lmin, lmax, m, mu.data());
-      double s = 0;
-      for (int k = 0; k <= m; ++k) s += mu[k] * tau[k];
-      return s;
-    };
+    NM_REQUIRE(!weighted || a > 0, NM_EINVAL, "weighted counts need a window above 0");
+    std::vector<double> mu;
+    auto count = [&](double x) { return dos_estimate(tau, m, lmin, lmax, a, x, weighted, mu); };
     const double total = count(b);
     edges[0] = a;
     for (int i = 1; i < nslices; ++i) {
@@ -371,6 +445,27 @@ nm_status nm_dos_slices(const double* tau, int32_t m, double lmin, double lmax, 
     }
     edges[nslices] = b;
   })
+}
+
+}  // namespace
+
+nm_status nm_dos_count(const double* tau, int32_t m, double lmin, double lmax, double a, double b, double* count) {
+  return dos_count_impl(tau, m, lmin, lmax, a, b, count, false);
+}
+
+nm_status nm_dos_count_weighted(const double* tau, int32_t m, double lmin, double lmax, double a, double b,
+                                double* count) {
+  return dos_count_impl(tau, m, lmin, lmax, a, b, count, true);
+}
+
+nm_status nm_dos_slices(const double* tau, int32_t m, double lmin, double lmax, double a, double b, int32_t nslices,
+                        double* edges) {
+  return dos_slices_impl(tau, m, lmin, lmax, a, b, nslices, edges, false);
+}
+
+nm_status nm_dos_slices_weighted(const double* tau, int32_t m, double lmin, double lmax, double a, double b,
+                                 int32_t nslices, double* edges) {
+  return dos_slices_impl(tau, m, lmin, lmax, a, b, nslices, edges, true);
 }
 
 nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, void* stream, double* lmin,

@@ -264,7 +264,7 @@ void b_apply(const nm_pencil* P, int ncols, const T* X, T* Y, const ApplyCfg& cf
 // density of states: tau_k = (1/s) sum_v z_v . T_k((B - c)/e) z_v, k = 0..m (host tau[m+1]),
 // Z device [n][s] in the internal node order
 void dos_traces(const nm_pencil* P, double lmin, double lmax, int m, int s, const double* Z, const ApplyCfg& cfg,
-                hipStream_t st, double* tau);
+                hipStream_t st, double* tau, bool weighted = false);
 // column dot products out[v] = sum_r X[r*ldx+v] Y[r*ldy+v] (deterministic)
 void col_dots(int64_t rows, int ncols, const double* X, int ldx, const double* Y, int ldy,
               double* out_dev, hipStream_t st);

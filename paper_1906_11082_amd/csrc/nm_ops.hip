@@ -1435,13 +1435,20 @@ void filter_apply_cols(const nm_pencil* P, const double* mu_cols, int m, double 
 // mass solve, no series accumulation) with the column dots of each step
 // reduced on the device in a fixed order.
 void dos_traces(const nm_pencil* P, double lmin, double lmax, int m, int s, const double* Z, const ApplyCfg& cfg,
-                hipStream_t st, double* tau) {
+                hipStream_t st, double* tau, bool weighted) {
   check_block(3 * P->N, s);
   NM_REQUIRE(m >= 0 && lmax > lmin, NM_EINVAL, "need m >= 0 and lmax > lmin");
   const int64_t n = 3 * P->N;
   const double c = 0.5 * (lmax + lmin), e = 0.5 * (lmax - lmin);
   FilterWork<double> w;
   w.ensure(P, s);
+  // weighted: the recurrence starts from B Z (traces of T_k((B - c)/e) B)
+  DBuf<double> bz;
+  if (weighted) {
+    bz.alloc((size_t)n * s);
+    b_apply_impl<double>(P, s, Z, bz.p, Update{}, cfg, w, st);
+  }
+  const double* start = weighted ? bz.p : Z;
   const int nblk = 512;
   DBuf<double> dots((size_t)(m + 1) * s), part((size_t)nblk * s);
   const int64_t rows_per = (n + nblk - 1) / nblk;
@@ -1449,10 +1456,10 @@ void dos_traces(const nm_pencil* P, double lmin, double lmax, int m, int s, cons
     hipLaunchKernelGGL(k_coldot_partial, dim3(nblk), dim3(256), 0, st, n, s, Z, s, W, s, rows_per, part.p);
     hipLaunchKernelGGL(k_coldot_final, dim3((s + 63) / 64), dim3(64), 0, st, nblk, s, part.p, dots.p + (size_t)k * s);
   };
-  coldot(Z, 0);
+  coldot(start, 0);
   double* bufs[2] = {w.w0.p, w.w1.p};
   const double* wprev = nullptr;
-  const double* win = Z;
+  const double* win = start;
   for (int k = 1; k <= m; ++k) {
     double* out = (wprev == bufs[0] || wprev == bufs[1]) ? (double*)wprev : (win == bufs[0] ? bufs[1] : bufs[0]);
     Update u;

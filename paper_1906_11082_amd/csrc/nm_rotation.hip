@@ -13,6 +13,9 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "nm_internal.h"
 
 namespace nm {
@@ -112,14 +115,23 @@ void rotation_residuals(const nm_pencil* P, nm_rot_result* r, hipStream_t st) {
   }
 }
 
-void project_rotation(const nm_pencil* P, const nm_eig_result* B, double a, double b, hipStream_t st,
-                      nm_rot_result** out) {
+namespace {
+
+// The projection of eq. "sublinear0" on an M-orthonormal basis X with
+// X^T A X = diag(lambda).  With lambda > 0 (eigenpairs of the pencil) the
+// mode's coefficients are the upper half of the Hermitian eigenvector over
+// sqrt(lambda); with zero_ok (a Rayleigh-Ritz basis that may hold rigid
+// motions or null-space directions, lambda >= 0) they are the lower half
+// over omega, which needs no division by sqrt(lambda).
+void project_core(const nm_pencil* P, const nm_eig_result* B, double a, double b, hipStream_t st,
+                  nm_rot_result** out, bool zero_ok) {
   auto t0 = std::chrono::steady_clock::now();
   NM_REQUIRE(B && B->count > 0 && B->X, NM_EINVAL, "empty basis");
   const int m = B->count;
   const int64_t n = B->n;
   NM_REQUIRE(n == 3 * P->N, NM_EINVAL, "basis does not belong to this pencil");
-  for (int i = 0; i < m; ++i) NM_REQUIRE(B->lambda[i] > 0, NM_EINVAL, "projection needs positive eigenvalues");
+  for (int i = 0; i < m; ++i)
+    NM_REQUIRE(zero_ok ? B->lambda[i] >= 0 : B->lambda[i] > 0, NM_EINVAL, "projection needs positive eigenvalues");
   NM_BLAS(rocblas_set_stream(P->blas, st));
   NM_BLAS(rocblas_set_pointer_mode(P->blas, rocblas_pointer_mode_host));
   DBuf<double> RX((size_t)n * m), Sd((size_t)m * m);
@@ -165,14 +177,15 @@ void project_rotation(const nm_pencil* P, const nm_eig_result* B, double a, doub
   r->n = n;
   r->omega = (double*)malloc(8 * std::max(k, 1));
   if (k > 0) {
-    // y = v[:m] / sqrt(lambda), normalised by y^H y - (i/w) y^H S y = 1
+    // y = v[:m] / sqrt(lambda) (or v[m:] / w), normalised by y^H y - (i/w) y^H S y = 1
     std::vector<double> Yr((size_t)m * k), Yi((size_t)m * k);
     for (int q = 0; q < k; ++q) {
       const int col = keep[q];
       const double om = w[col];
       r->omega[q] = om;
       std::vector<std::complex<double>> y(m);
-      for (int i = 0; i < m; ++i) y[i] = H[i + (size_t)col * n2] / std::sqrt(B->lambda[i]);
+      for (int i = 0; i < m; ++i)
+        y[i] = zero_ok ? H[(m + i) + (size_t)col * n2] / om : H[i + (size_t)col * n2] / std::sqrt(B->lambda[i]);
       std::complex<double> yy = 0, ysy = 0;
       for (int i = 0; i < m; ++i) {
         yy += std::conj(y[i]) * y[i];
@@ -203,6 +216,13 @@ void project_rotation(const nm_pencil* P, const nm_eig_result* B, double a, doub
   rotation_residuals(P, r, st);
   r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = r;
+}
+
+}  // namespace
+
+void project_rotation(const nm_pencil* P, const nm_eig_result* B, double a, double b, hipStream_t st,
+                      nm_rot_result** out) {
+  project_core(P, B, a, b, st, out, false);
 }
 
 namespace {
@@ -267,6 +287,7 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
   NM_REQUIRE(iters >= 0 && tol > 0, NM_EINVAL, "need iters >= 0 and tol > 0");
   const int64_t n = B->n, N = P->N;
   const int m0 = B->count;
+  const bool verbose = std::getenv("NM_REFINE_VERBOSE") != nullptr;
   const int d = degree > 0 ? degree
                            : std::min(2000, std::max(100, (int)std::ceil(20.0 * std::sqrt(B->lmax / b))));
   NM_BLAS(rocblas_set_stream(P->blas, st));
@@ -291,8 +312,6 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
   nm_rot_result* cur = nullptr;  // owned once refined
   const nm_rot_result* src = R0;
   int done_iters = 0;
-  std::vector<double> res0(R0->count);
-  if (R0->resid) std::copy(R0->resid, R0->resid + R0->count, res0.begin());
   for (int it = 0; it < iters; ++it) {
     const int k = src->count;
     if (k == 0) break;
@@ -357,15 +376,24 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
     NM_HIP(hipStreamSynchronize(st));
     std::vector<double> dsc(nc);
     for (int i = 0; i < nc; ++i) dsc[i] = Gh[i + (size_t)i * nc] > 0 ? 1.0 / std::sqrt(Gh[i + (size_t)i * nc]) : 0.0;
-    for (int q = 0; q < nc; ++q)
-      for (int i = 0; i < nc; ++i)
-        Gh[i + (size_t)q * nc] = dsc[i] * 0.5 * (Gh[i + (size_t)q * nc] + Gh[q + (size_t)i * nc]) * dsc[q];
+    {
+      // symmetrised and scaled to unit diagonal, into a fresh array (in place,
+      // the second of each pair would read an already scaled partner)
+      std::vector<double> Gs((size_t)nc * nc);
+      for (int q = 0; q < nc; ++q)
+        for (int i = 0; i < nc; ++i)
+          Gs[i + (size_t)q * nc] = dsc[i] * 0.5 * (Gh[i + (size_t)q * nc] + Gh[q + (size_t)i * nc]) * dsc[q];
+      Gh.swap(Gs);
+    }
     sym_eig_dev(h, nc, Gh, gw, st);
     const double gmax = gw.empty() ? 0.0 : gw.back();
     std::vector<int> keep;
     for (int i = 0; i < nc; ++i)
       if (gw[i] > 1e-10 * gmax) keep.push_back(i);
     const int r = (int)keep.size();
+    if (verbose)
+      fprintf(stderr, "[nmodes] refine pass %d: %d modes, max resid %.3e, corrections %d of %d kept (Gram %.3e .. %.3e)\n",
+              it, k, rmax, r, nc, gw.empty() ? 0.0 : gw.front(), gmax);
     if (r == 0) break;
     std::vector<double> Cm((size_t)nc * r);
     for (int c2 = 0; c2 < r; ++c2)
@@ -391,14 +419,19 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
     for (int q = 0; q < m; ++q)
       for (int i = 0; i < q; ++i) Kh[i + (size_t)q * m] = Kh[q + (size_t)i * m] = 0.5 * (Kh[i + (size_t)q * m] + Kh[q + (size_t)i * m]);
     sym_eig_dev(h, m, Kh, kw, st);
+    // every direction of the enlarged span is kept, rigid motions and null
+    // directions (K-eigenvalue ~ 0) included -- dropping them loses the
+    // coupling the refinement is for; directions of clearly negative K (the
+    // gravitational terms make A indefinite on a few) have no real frequency
+    // and are left out
     const double kmx = kw.empty() ? 0.0 : kw.back();
     std::vector<int> kk;
     for (int i = 0; i < m; ++i)
-      if (kw[i] > 1e-10 * kmx) kk.push_back(i);
+      if (kw[i] >= -1e-10 * kmx) kk.push_back(i);
     const int mk = (int)kk.size();
     std::vector<double> Qk((size_t)m * mk), lam(mk);
     for (int q = 0; q < mk; ++q) {
-      lam[q] = kw[kk[q]];
+      lam[q] = std::max(0.0, kw[kk[q]]);
       std::copy(Kh.begin() + (size_t)kk[q] * m, Kh.begin() + (size_t)(kk[q] + 1) * m, Qk.begin() + (size_t)q * m);
     }
     DBuf<double> Qd((size_t)m * mk), W((size_t)n * mk);
@@ -412,7 +445,21 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
     tmp.lambda = lam.data();
     tmp.X = W.p;
     nm_rot_result* rn = nullptr;
-    project_rotation(P, &tmp, a, b, st, &rn);
+    project_core(P, &tmp, a, b, st, &rn, true);
+    // a pass is kept only if every mode it returns has a residual below the
+    // previous pass's largest: Rayleigh-Ritz for the QEP has no min-max
+    // principle, and on the enlarged span it can return spurious window
+    // values with large residuals (measured on a small fluid planet); the
+    // refinement then stops at its best pass
+    double rn_max = 0.0;
+    for (int v = 0; v < rn->count; ++v) rn_max = std::max(rn_max, rn->resid[v]);
+    if (verbose)
+      fprintf(stderr, "[nmodes] refine pass %d: basis %d (K %.3e .. %.3e, %d kept), %d modes, max resid %.3e\n", it,
+              m, kw.empty() ? 0.0 : kw.front(), kmx, mk, rn->count, rn_max);
+    if (rn->count == 0 || !(rn_max < rmax)) {
+      nm_rot_result_free(rn);
+      break;
+    }
     if (cur) nm_rot_result_free(cur);
     cur = rn;
     src = cur;

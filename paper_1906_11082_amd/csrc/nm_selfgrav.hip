@@ -26,6 +26,9 @@
 #include <cstring>
 #include <numeric>
 
+#include <cstdlib>
+#include <string>
+
 #include "nm_internal.h"
 
 namespace {
@@ -109,6 +112,126 @@ __global__ __launch_bounds__(256) void k_nbody(int64_t nb, int nc, const float4*
     if (c0 + c >= nc) break;
     phi[i * nc + c0 + c] = G * (acc[c] + invR[i] * q64[i * nc + c0 + c]);
   }
+}
+
+// The same sums register-blocked: each lane owns TPL targets (i0 + t 256 +
+// lane, so the loads stay coalesced) and reuses every staged source (its
+// position and CB charges, read from LDS as float4s) for all of them; the
+// inner loop over a full tile is unrolled, and only tiles that hold one of
+// the workgroup's own targets test for the self pair.  The sources are split
+// into runs (blockIdx.z) so that a launch has enough workgroups to fill the
+// chip even for few columns; each run writes its FP64 partial sums, which
+// k_nbody_reduce adds in run order.  CB is a multiple of 4.
+template <int CB, int TPL>
+__global__ __launch_bounds__(256) void k_nbody_rb(int64_t nb, int nc, const float4* __restrict__ pos,
+                                                  const float* __restrict__ q, int64_t span,
+                                                  double* __restrict__ part) {
+  constexpr int CQ = CB / 4;
+  __shared__ float4 s_pos[NB_TILE];
+  __shared__ float4 s_q[NB_TILE][CQ];
+  const int64_t i0 = (int64_t)blockIdx.x * (256 * TPL);
+  const int c0 = blockIdx.y * CB;
+  int64_t ii[TPL];
+  float4 pi[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    ii[t] = i0 + t * 256 + threadIdx.x;
+    pi[t] = ii[t] < nb ? pos[ii[t]] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  double acc[TPL][CB];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[t][c] = 0.0;
+  // this workgroup's run of sources: [js, je), span a multiple of NB_TILE
+  const int64_t js = (int64_t)blockIdx.z * span, je = min<int64_t>(nb, js + span);
+  for (int64_t j0 = js; j0 < je; j0 += NB_TILE) {
+    __syncthreads();
+    {
+      const int64_t j = j0 + threadIdx.x;
+      s_pos[threadIdx.x] = j < nb ? pos[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int cq = 0; cq < CQ; ++cq) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + 4 * cq + u;
+          v[u] = (j < nb && c < nc) ? q[j * nc + c] : 0.f;
+        }
+        s_q[threadIdx.x][cq] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+    __syncthreads();
+    float tsum[TPL][CB];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) tsum[t][c] = 0.f;
+    const int lim = (int)min<int64_t>(NB_TILE, nb - j0);
+    const bool own = j0 < i0 + 256 * TPL && j0 + NB_TILE > i0;
+    if (!own && lim == NB_TILE) {
+#pragma unroll 4
+      for (int jj = 0; jj < NB_TILE; ++jj) {
+        const float4 pj = s_pos[jj];
+        float qq[CB];
+#pragma unroll
+        for (int cq = 0; cq < CQ; ++cq) {
+          const float4 v = s_q[jj][cq];
+          qq[4 * cq] = v.x; qq[4 * cq + 1] = v.y; qq[4 * cq + 2] = v.z; qq[4 * cq + 3] = v.w;
+        }
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+          const float dx = pi[t].x - pj.x, dy = pi[t].y - pj.y, dz = pi[t].z - pj.z;
+          const float ir = rsqrtf(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+          for (int c = 0; c < CB; ++c) tsum[t][c] += qq[c] * ir;
+        }
+      }
+    } else {
+      for (int jj = 0; jj < lim; ++jj) {
+        const float4 pj = s_pos[jj];
+        float qq[CB];
+#pragma unroll
+        for (int cq = 0; cq < CQ; ++cq) {
+          const float4 v = s_q[jj][cq];
+          qq[4 * cq] = v.x; qq[4 * cq + 1] = v.y; qq[4 * cq + 2] = v.z; qq[4 * cq + 3] = v.w;
+        }
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+          const float dx = pi[t].x - pj.x, dy = pi[t].y - pj.y, dz = pi[t].z - pj.z;
+          const float ir = (j0 + jj == ii[t]) ? 0.f : rsqrtf(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+          for (int c = 0; c < CB; ++c) tsum[t][c] += qq[c] * ir;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[t][c] += (double)tsum[t][c];
+  }
+  // partial sums of this source run: part[z][i][c]
+  double* pz = part + (int64_t)blockIdx.z * nb * nc;
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    if (ii[t] >= nb) continue;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      if (c0 + c >= nc) break;
+      pz[ii[t] * nc + c0 + c] = acc[t][c];
+    }
+  }
+}
+
+// phi = G (sum over the source runs in order + invR q): deterministic
+__global__ void k_nbody_reduce(int64_t nb, int nc, int nsplit, const double* __restrict__ part,
+                               const double* __restrict__ invR, const double* __restrict__ q64, double G,
+                               double* __restrict__ phi) {
+  const int64_t g = gtid();
+  if (g >= nb * nc) return;
+  double s = 0.0;
+  for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * nb * nc + g];
+  phi[g] = G * (s + invR[g / nc] * q64[g]);
 }
 
 // reference field g(x_p) = -G sum_k m_k (x_p - r_k) / |x_p - r_k|^3 (FP32 pairs, FP64 tile sums)
@@ -272,8 +395,11 @@ struct nm_selfgrav {
   DBuf<double> c_val, ct_val;
   // work buffers of apply (sized for the widest block seen; one caller at a time)
   int wcols = 0;
-  DBuf<double> q64, phi;
+  DBuf<double> q64, phi, part;
   DBuf<float> q32;
+  void ensure_part(size_t elems) {
+    if (part.n < elems) part.alloc(elems);
+  }
   void ensure(int nc) {
     if (nc <= wcols) return;
     q64.alloc((size_t)nbody * nc);
@@ -292,10 +418,28 @@ void selfgrav_add(const nm_selfgrav* sgc, int nc, const double* X, double* F, hi
   const int64_t nb = sg->nbody, n = 3 * sg->P->N;
   hipLaunchKernelGGL(k_csr_cols, dim3(grid_for(nb * nc)), dim3(256), 0, st, nb, nc, sg->c_ptr.p, sg->c_col.p,
                      sg->c_val.p, X, 1.0, sg->q64.p, sg->q32.p);
-  constexpr int CB = 8;
-  dim3 grid((unsigned)((nb + 255) / 256), (unsigned)((nc + CB - 1) / CB));
-  hipLaunchKernelGGL((k_nbody<CB>), grid, dim3(256), 0, st, nb, nc, sg->pos.p, sg->q32.p, sg->invR.p, sg->q64.p,
-                     sg->G, sg->phi.p);
+  // kernel: NM_NBODY=simple (one target per lane, for comparison) or the
+  // default: two targets per lane, LDS-staged sources split into runs
+  const char* kn = std::getenv("NM_NBODY");
+  constexpr int CB = 8, TPL = 2;
+  if (kn && std::string(kn) == "simple") {
+    dim3 grid((unsigned)((nb + 255) / 256), (unsigned)((nc + CB - 1) / CB));
+    hipLaunchKernelGGL((k_nbody<CB>), grid, dim3(256), 0, st, nb, nc, sg->pos.p, sg->q32.p, sg->invR.p, sg->q64.p,
+                       sg->G, sg->phi.p);
+  } else {
+    const int64_t bx = (nb + 256 * TPL - 1) / (256 * TPL), by = (nc + CB - 1) / CB;
+    const int64_t tiles = (nb + NB_TILE - 1) / NB_TILE;
+    // about 2048 workgroups, at least one source tile per run, at most 16 runs
+    const int64_t want = std::min<int64_t>(16, std::max<int64_t>(1, (2048 + bx * by - 1) / (bx * by)));
+    const int64_t span = NB_TILE * ((tiles + want - 1) / want);
+    const int nsplit = (int)((nb + span - 1) / span);
+    sg->ensure_part((size_t)nsplit * nb * nc);
+    dim3 grid((unsigned)bx, (unsigned)by, (unsigned)nsplit);
+    hipLaunchKernelGGL((k_nbody_rb<CB, TPL>), grid, dim3(256), 0, st, nb, nc, sg->pos.p, sg->q32.p, span,
+                       sg->part.p);
+    hipLaunchKernelGGL(k_nbody_reduce, dim3(grid_for(nb * nc)), dim3(256), 0, st, nb, nc, nsplit, sg->part.p,
+                       sg->invR.p, sg->q64.p, sg->G, sg->phi.p);
+  }
   // F -= C^T phi: the scattered term is added with the sign folded into phi's use
   hipLaunchKernelGGL(k_csr_cols_add, dim3(grid_for(n * nc)), dim3(256), 0, st, n, nc, sg->ct_ptr.p, sg->ct_col.p,
                      sg->ct_val.p, sg->phi.p, F);

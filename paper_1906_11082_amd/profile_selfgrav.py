@@ -4,7 +4,8 @@
 
 Builds the bodies of the three-layer planet at n_half (tetrahedra, surface
 and fluid-solid faces), then times nm_selfgrav_apply (charges C X, the
-direct N-body sums S q, the scatter C^T) on `cols` columns with HIP events,
+direct N-body sums S q, the scatter C^T) on `cols` columns with HIP events
+(the N-body kernel variant from the NM_NBODY environment variable),
 and the reference field at the vertices.  Reports pairs per second and the
 FP32 rate of the N-body kernel against the 157.3 TFLOP/s FP32 vector peak,
 counting per pair and column one FMA (2 flops) and per pair 8 flops for the
@@ -65,6 +66,7 @@ def main():
     fms = t0.elapsed_time(t1)
     fpairs = float(pts.shape[0]) * sg.n_tet
     print(json.dumps(dict(
+        kernel=os.environ.get("NM_NBODY", "split"),
         workload="self-gravitation of the three-layer planet, %d tets, %d bodies (%d faces), %d columns"
                  % (len(d["tet"]), nb, sg.n_face, args.cols),
         build_ms=build_ms, apply_ms=ms, pairs_per_s=pairs / (ms * 1e-3),

@@ -156,3 +156,15 @@ def test_dos_count_and_slices_match_oracle(lib):
         e1 = nm.dos_slices(tau, lmin, lmax, a, b, 4)
         e2 = D.slice_edges(tau, lmin, lmax, a, b, 4)
         assert np.abs(e1 - e2).max() <= 1e-9 * b
+    # weighted traces (null-free): the library's panel quadrature of the 1/lambda
+    # series against the oracle's adaptive quadrature
+    lam = np.concatenate([np.zeros(3000), lam])
+    tw = D.exact_traces(lam, lmin, lmax, 700, weighted=True)
+    for a, b in [(1.0, 60.0), (5.0, 400.0)]:
+        cw = nm.dos_count(tw, lmin, lmax, a, b, weighted=True)
+        assert abs(cw - D.window_count(tw, lmin, lmax, a, b, weighted=True)) <= 1e-8 * len(lam)
+        e1 = nm.dos_slices(tw, lmin, lmax, a, b, 3, weighted=True)
+        e2 = D.slice_edges(tw, lmin, lmax, a, b, 3, weighted=True)
+        assert np.abs(e1 - e2).max() <= 1e-7 * b
+    with pytest.raises(nm.NMError):
+        nm.dos_count(tw, lmin, lmax, 0.0, 10.0, weighted=True)

@@ -51,3 +51,38 @@ def test_dos_traces_match_oracle():
     print("count [1, 12] (lmax %.4g): estimates %s, mean %.2f +- %.2f, oracle %d"
           % (lmax, np.round(est, 1), est.mean(), se, len(w)), flush=True)
     assert abs(est.mean() - len(w)) <= 4.0 * se + 1.0
+
+
+def test_weighted_dos_matches_oracle_and_counts():
+    """Null-free traces (recurrence from B z) on the GPU equal the oracle's
+    (1e-9 of the largest, degree 200); at degree 3000 the weighted count of
+    [1, 12] is the stored window count within the sampling error and one
+    eigenvalue (the smoothing of 1/lambda near the window's lower end)."""
+    import torch
+    import paper_1906_11082_amd as nm
+    from oracle import dos as D
+    from oracle import solve as S
+    d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    O = oracle_pencil("three_layer_planet", n_half=4, order=2, pres_order=1)
+    G = nm.Pencil(d)
+    lo, hi = G.spectrum_bounds(60, 3)
+    lmin, lmax = lo - 0.01, hi
+    Zh = np.random.default_rng(9).standard_normal((G.n, 16))
+    tau = G.spectrum_dos(lmin, lmax, 200, torch.from_numpy(Zh).cuda(), weighted=True, minv_tol=1e-12, kp_tol=1e-13)
+    op = S.CowlingOperator(O, minv_tol=1e-12, kp_tol=1e-13)
+    ref = D.kpm_traces(op.B, Zh, lmin, lmax, 200, weighted=True)
+    err = np.abs(tau - ref).max() / np.abs(ref).max()
+    print("weighted dos traces: max rel difference %.2e" % err, flush=True)
+    assert err <= 1e-9
+    w = np.loadtxt(os.path.join(HERE, "golden", "cowling_window_nh4.txt"))
+    g = torch.Generator(device="cuda").manual_seed(12)
+    est = []
+    for _ in range(8):
+        Zg = torch.randn(G.n, 16, generator=g, dtype=torch.float64, device="cuda")
+        t = G.spectrum_dos(lmin, lmax, 3000, Zg, weighted=True, minv_tol=1e-12, kp_tol=1e-13)
+        est.append(nm.dos_count(t, lmin, lmax, 1.0, 12.0, weighted=True))
+    est = np.array(est)
+    se = est.std(ddof=1) / np.sqrt(len(est))
+    print("weighted count [1, 12]: estimates %s, mean %.2f +- %.2f, oracle %d"
+          % (np.round(est, 1), est.mean(), se, len(w)), flush=True)
+    assert abs(est.mean() - len(w)) <= 4.0 * se + 1.0
