@@ -440,22 +440,22 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
 
 // sum over the group's union columns of coef[., r] X[col] for the R rows;
 // cl / cf as in row_spmv (LDS or global arrays, entry l at l - base)
-template <class T, int V, int R>
+template <class T, int V, int R, int U = 4>
 __device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_t base, int32_t l0, int32_t l1,
                                           const T* __restrict__ X, uint32_t w, uint32_t e, Vx<T, V> (&acc)[R]) {
-  for (int32_t l = l0; l < l1; l += 4) {
-    uint32_t c[4];
-    bool in[4];
+  for (int32_t l = l0; l < l1; l += U) {
+    uint32_t c[U];
+    bool in[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       in[u] = l + u < l1;
       c[u] = (uint32_t)cl[(in[u] ? l + u : l0) - base];
     }
-    Vx<T, V> x[4];
+    Vx<T, V> x[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
+    for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const T* a = cf + (size_t)((in[u] ? l + u : l0) - base) * R;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -476,7 +476,7 @@ __device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_
 // bound the step through the texture-address unit) drops by the ratio of
 // the rows' entries to the size of their union.  Union columns and
 // coefficients of the workgroup's groups are staged in LDS.
-template <class T, int V, int R>
+template <class T, int V, int R, int U = 4>
 __global__ __launch_bounds__(256) void k_cj_group(
     uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
     const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
@@ -508,9 +508,9 @@ __global__ __launch_bounds__(256) void k_cj_group(
     for (int i = 0; i < V; ++i) acc[r].v[i] = T(0);
   const int32_t l0 = gptr[grp], l1 = gptr[grp + 1];
   if (staged)
-    group_sum<T, V, R>(s_col, s_cf, lb, l0, l1, ycur, w, e, acc);
+    group_sum<T, V, R, U>(s_col, s_cf, lb, l0, l1, ycur, w, e, acc);
   else
-    group_sum<T, V, R>(gcol, gcoef, 0, l0, l1, ycur, w, e, acc);
+    group_sum<T, V, R, U>(gcol, gcoef, 0, l0, l1, ycur, w, e, acc);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t row = r0 + r;
@@ -1017,8 +1017,16 @@ void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const
   hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,     \
                      tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,  \
                      cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
+  static const int unroll = [] {
+    const char* u = std::getenv("NM_GROUP_UNROLL");  // gathers in flight per lane (4 or 8)
+    return u && std::atoi(u) == 8 ? 8 : 4;
+  }();
   if (tp.R == 8) {
     if (v == 4) NM_GRP(4, 8); else if (v == 2) NM_GRP(2, 8); else NM_GRP(1, 8);
+  } else if (unroll == 8 && v == 4) {
+    hipLaunchKernelGGL((k_cj_group<T, 4, 4, 8>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,
+                       tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,
+                       cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc);
   } else {
     if (v == 4) NM_GRP(4, 4); else if (v == 2) NM_GRP(2, 4); else NM_GRP(1, 4);
   }

@@ -10,9 +10,10 @@ The three-layer planet (P2/P1, Cowling) rotating about z:
    polynomial method on B z, so the fluid null space at 0 does not leak into
    the counts; Sec. 6.1's spectrum slicing) give `slices` windows of [a, b]
    with equal estimated eigenvalue counts;
-2. the slices are solved in one batched call, each with the two-sided slice
-   filter (damping beyond bands of `guard` slice widths on both sides),
-   their filter applications concatenated;
+2. the slices are solved in one batched call (or one after another with
+   --sequential), each with the two-sided slice filter (damping beyond bands
+   of `guard` slice widths on both sides), their filter applications
+   concatenated (series zero-padded to the largest degree);
 3. the whole window [a, b] is solved once for comparison (unless
    --skip-window): counts, eigenvalues and column B-applications;
 4. the Coriolis problem (Sec. 7) is projected on the window's modes at the
@@ -71,6 +72,9 @@ def main():
     ap.add_argument("--skip-slices", action="store_true")
     ap.add_argument("--skip-rotation", action="store_true")
     ap.add_argument("--guard", type=float, default=1.0, help="slice filter bands, in slice widths")
+    ap.add_argument("--sequential", action="store_true",
+                    help="solve the slices one after another, each with its own filter degree, instead of one "
+                         "batched call (whose series are padded to the largest degree)")
     ap.add_argument("--save", default="", help="write the eigenvalues found to this .npz")
     args = ap.parse_args()
     import numpy as np
@@ -103,13 +107,18 @@ def main():
                                                                  out["dos"]["seconds"]))
         wins = [(float(edges[i]), float(edges[i + 1])) for i in range(args.slices)]
         t = time.time()
-        rs = P.filtered_eig_slices(wins, args.nev, args.tol, lmin=lmin, lmax=lmax, null_filter=3, guard=args.guard, seed=9,
-                                   verbose=1, **kw)
+        if args.sequential:
+            rs = [P.filtered_eig(a, b, args.nev, args.tol, lmin=lmin, lmax=lmax, null_filter=3, guard=args.guard,
+                                 seed=9, verbose=1, **kw) for a, b in wins]
+        else:
+            rs = P.filtered_eig_slices(wins, args.nev, args.tol, lmin=lmin, lmax=lmax, null_filter=3,
+                                       guard=args.guard, seed=9, verbose=1, **kw)
         torch.cuda.synchronize()
         dt = time.time() - t
         lam_s = np.concatenate([r.lam for r in rs])
         bapps = sum(r.stats["bapps"] + r.stats["refine_bapps"] for r in rs)
-        out["slices"] = dict(seconds=dt, count=int(len(lam_s)), column_bapps=int(bapps),
+        out["slices"] = dict(seconds=dt, count=int(len(lam_s)), column_bapps=int(bapps), sequential=args.sequential,
+                             guard=args.guard,
                              per_slice=[dict(window=w, count=r.count, degree=r.stats["degree"], basis=r.stats["basis"],
                                              resid_max=float(r.resid.max()) if r.count else None,
                                              bapps=r.stats["bapps"], refine_bapps=r.stats["refine_bapps"])

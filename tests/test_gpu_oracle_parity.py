@@ -93,21 +93,21 @@ def test_autotuned_solve_matches_oracle():
     check_against_oracle(r, w, X, O.M, rel=1e-9, resid=1e-9)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_graph_replayed_solve_matches_oracle(monkeypatch, precision):
-    """The filter captured once in a HIP graph and replayed for every block:
-    the C1 ball's 30 lowest pairs equal the oracle's dense solve."""
+@pytest.mark.parametrize("precision,mass_passes", [(0, 0), (1, 0), (0, 2)])
+def test_graph_replayed_solve_matches_oracle(monkeypatch, precision, mass_passes):
+    """The filter captured once in a HIP graph and replayed for every block
+    (FP64, FP32 filter, and FP64 with the mixed-precision mass solve): the
+    C1 ball's 30 lowest pairs equal the oracle's dense solve."""
     import paper_1906_11082_amd as nm
     from oracle import solve as S
     d = make_planet("homogeneous_ball", n_half=4, order=1)
     O = oracle_pencil("homogeneous_ball", n_half=4, order=1)
     monkeypatch.setenv("NM_GRAPH", "1")
     G = nm.Pencil(d)
-    tol = 1e-10 if precision == 0 else 1e-8
-    r = G.filtered_eig(0.5, 40.0, 30, tol, degree=40, block=8, precision=precision)
+    tol = 1e-10 if precision == 0 and mass_passes == 0 else 1e-8
+    r = G.filtered_eig(0.5, 40.0, 30, tol, degree=40, block=8, precision=precision, mass_passes=mass_passes)
     w, X = S.dense_window(O.AG.toarray(), O.M.toarray(), 0.5, 40.0)
-    check_against_oracle(r, w, X, O.M, rel=1e-10 if precision == 0 else 1e-8, resid=tol, nev=30,
-                         proj=1e-7 if precision == 0 else 1e-6)
+    check_against_oracle(r, w, X, O.M, rel=tol, resid=tol, nev=30, proj=1e-7 if tol < 1e-9 else 1e-6)
 
 
 def test_rotating_fluid_planet_projection():
