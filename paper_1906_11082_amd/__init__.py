@@ -31,7 +31,7 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_result_copy_vectors", "nm_rot_copy_vectors", "nm_result_free", "nm_rot_result_free",
             "nm_pencil_free", "nm_last_error", "nm_version", "nm_set_allocator", "nm_max_block_columns", "nm_pencil_apply_noalloc",
             "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices", "nm_spectrum_dos_weighted", "nm_dos_count_weighted",
-            "nm_dos_slices_weighted", "nm_refine_rotation",
+            "nm_dos_slices_weighted", "nm_spectrum_bound_rigorous", "nm_refine_rotation",
             "nm_selfgrav_build", "nm_selfgrav_info", "nm_selfgrav_apply", "nm_selfgrav_field",
             "nm_pencil_attach_selfgrav", "nm_selfgrav_free"]
 
@@ -174,6 +174,7 @@ def load_library(path: str | None = None):
                                       P], C.c_int32),
         "nm_dos_count_weighted": ([P, C.c_int32] + [C.c_double] * 4 + [C.POINTER(C.c_double)], C.c_int32),
         "nm_dos_slices_weighted": ([P, C.c_int32] + [C.c_double] * 4 + [C.c_int32, P], C.c_int32),
+        "nm_spectrum_bound_rigorous": ([P, P, C.POINTER(C.c_double)], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -433,6 +434,12 @@ class Pencil:
         Z = torch.randn(self.n, nvec, generator=g, dtype=torch.float64, device="cuda")
         tau = self.spectrum_dos(lmin, lmax, m, Z, weighted=weighted)
         return dos_slices(tau, lmin, lmax, a, b, nslices, weighted=weighted), tau
+
+    def spectrum_bound_rigorous(self):
+        """An upper bound of the pencil's spectrum that provably holds (nm_spectrum_bound_rigorous)."""
+        hi = C.c_double()
+        _check(_lib.nm_spectrum_bound_rigorous(self._h, _stream(), C.byref(hi)))
+        return hi.value
 
     def spectrum_bounds(self, steps=60, seed=1):
         lo, hi = C.c_double(), C.c_double()

@@ -468,6 +468,13 @@ nm_status nm_dos_slices_weighted(const double* tau, int32_t m, double lmin, doub
   return dos_slices_impl(tau, m, lmin, lmax, a, b, nslices, edges, true);
 }
 
+nm_status nm_spectrum_bound_rigorous(const nm_pencil* p, void* stream, double* lmax) {
+  NM_TRY({
+    NM_REQUIRE(p && lmax, NM_EINVAL, "invalid arguments");
+    *lmax = nm::lmax_rigorous(p, (hipStream_t)stream);
+  })
+}
+
 nm_status nm_spectrum_bounds(const nm_pencil* p, int32_t steps, uint64_t seed, void* stream, double* lmin,
                              double* lmax) {
   NM_TRY({

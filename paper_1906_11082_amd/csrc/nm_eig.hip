@@ -231,6 +231,77 @@ struct Timer {
 
 }  // namespace
 
+namespace {
+
+// w_p = sum over the displacement DOFs (j, b) of |E_G[(j, b), p]| / sqrt(M_s,jj)
+__global__ void k_bound_w(int64_t np, const int32_t* __restrict__ tp, const int32_t* __restrict__ tc,
+                          const double* __restrict__ tv, const double* __restrict__ mdinv, double* __restrict__ w) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double s = 0.0;
+  for (int32_t k = tp[p]; k < tp[p + 1]; ++k)
+    s += (fabs(tv[3 * (int64_t)k]) + fabs(tv[3 * (int64_t)k + 1]) + fabs(tv[3 * (int64_t)k + 2])) * sqrt(mdinv[tc[k]]);
+  w[p] = s;
+}
+
+// per node i, the largest over its three DOFs a of the Gershgorin row sum of
+// D^{-1/2} A_G D^{-1/2} plus the row bound of D^{-1/2} E_G D_p^{-1} E_G^T D^{-1/2} / theta_p
+__global__ void k_bound_rows(int64_t N, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const double* __restrict__ ag, const double* __restrict__ mdinv,
+                             const int32_t* __restrict__ ep, const int32_t* __restrict__ ec,
+                             const double* __restrict__ ev, const double* __restrict__ w,
+                             const double* __restrict__ kpdinv, double inv_theta_p, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double si = sqrt(mdinv[i]);
+  double best = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double g = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const double* blk = ag + 9 * (int64_t)k + 3 * a;
+      g += (fabs(blk[0]) + fabs(blk[1]) + fabs(blk[2])) * si * sqrt(mdinv[col[k]]);
+    }
+    double e = 0.0;
+    if (ep)
+      for (int32_t k = ep[i]; k < ep[i + 1]; ++k) e += fabs(ev[3 * (int64_t)k + a]) * w[ec[k]] * kpdinv[ec[k]] * si;
+    best = fmax(best, g + inv_theta_p * e);
+  }
+  out[i] = best;
+}
+
+}  // namespace
+
+// A bound that holds for every eigenvalue of the Cowling pencil (A, M),
+// A = A_G + E_G K_p^{-1} E_G^T, with D = diag(M):
+//   x^T M x >= theta_M x^T D x  (theta_M the reference element's lower Jacobi
+//   bound of M, valid for the assembled matrix), K_p >= theta_p D_p likewise,
+//   so lambda_max <= [max row sum of |D^{-1/2} A_G D^{-1/2}|
+//                     + max row bound of D^{-1/2} E_G D_p^{-1} E_G^T D^{-1/2} / theta_p] / theta_M
+// (Gershgorin; the Schur row bound from sum_p |E_ip| w_p / D_p,pp).  Looser
+// than the Lanczos estimate, so the filter is built on the estimate and the
+// bound serves the blow-up restart.  Without the self-gravitation term.
+double lmax_rigorous(const nm_pencil* P, hipStream_t st) {
+  const int64_t N = P->N, np = P->n_pres;
+  DBuf<double> rows(N);
+  DBuf<double> w(std::max<int64_t>(np, 1));
+  const bool fl = np > 0;
+  if (fl)
+    hipLaunchKernelGGL(k_bound_w, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np, P->egt_ptr.p,
+                       P->egt_col.p, P->egt_val.p, P->mdinv.p, w.p);
+  hipLaunchKernelGGL(k_bound_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, P->row_ptr.p, P->col.p,
+                     P->ag.p, P->mdinv.p, fl ? P->eg_ptr.p : nullptr, fl ? P->eg_col.p : nullptr,
+                     fl ? P->eg_val.p : nullptr, w.p, fl ? P->kpdinv.p : nullptr, fl ? 1.0 / P->ref.p_lo : 0.0,
+                     rows.p);
+  NM_HIP(hipGetLastError());
+  std::vector<double> h(N);
+  NM_HIP(hipMemcpyAsync(h.data(), rows.p, 8 * N, hipMemcpyDeviceToHost, st));
+  NM_HIP(hipStreamSynchronize(st));
+  double mx = 0.0;
+  for (double v : h) mx = std::max(mx, v);
+  return mx / P->ref.m_lo;
+}
+
+
 // Bounds of spec(M^{-1} A) from `steps` Lanczos steps in the M-inner
 // product (full reorthogonalisation): lmax = 1.01 (theta_max + |beta s|),
 // a safe upper bound once the top Ritz value has converged;
@@ -322,8 +393,9 @@ static void filtered_eig_once(const nm_pencil* P, double a, double b, int nev, d
 
 // A blow-up means the bound lambda_max was below the spectrum (the filter's
 // Chebyshev polynomials grow without limit beyond their interval): the solve
-// restarts on [lmin, max(2 lmax, 1.5 x a fresh 120-step Lanczos estimate)], at
-// most three times.  Batched solves share one interval and report the error.
+// restarts on [lmin, max(2 lmax, 1.5 x a fresh 120-step Lanczos estimate)], the
+// third time on the rigorous bound of lmax_rigorous; batched solves share one
+// interval and report the error.
 void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, const nm_eig_opts& o,
                   nm_eig_result** out, BatchSeat* seat, rocblas_handle blas) {
   nm_eig_opts oo = o;
@@ -337,6 +409,8 @@ void filtered_eig(const nm_pencil* P, double a, double b, int nev, double tol, c
       spectrum_bounds(P, 120, o.seed ^ 0x2545f491ull, (hipStream_t)o.stream, &lo, &hi);
       oo.lmin = std::min(e.lmin, lo - 1e-3 * (b - a));
       oo.lmax = std::max(2.0 * e.lmax, 1.5 * hi);
+      // the last attempt takes the rigorous bound (when no self-gravitation term is attached)
+      if (attempt == 2 && !P->selfgrav) oo.lmax = std::max(oo.lmax, lmax_rigorous(P, (hipStream_t)o.stream));
       if (o.verbose)
         fprintf(stderr, "[nmodes] filter blow-up with lambda_max %.6g: restarting on [%.6g, %.6g]\n", e.lmax, oo.lmin,
                 oo.lmax);
@@ -867,6 +941,12 @@ static void filtered_eig_once(const nm_pencil* P, double a, double b, int nev, d
         filter_apply<double>(P, muq.data(), kq, cq, eq, 0.0, nullf ? b : 0.0, nc, T2.p, W.p, cfgq, fw, st);
         NM_HIP(hipMemcpy2DAsync(Yq.p + j0, 8 * (size_t)q, W.p, 8 * (size_t)nc, 8 * (size_t)nc, n,
                                 hipMemcpyDeviceToDevice, st));
+        if (o.verbose) {
+          // progress of long refinements (an FP32 basis needs a high degree on many vectors)
+          NM_HIP(hipStreamSynchronize(st));
+          fprintf(stderr, "[nmodes] refine pass %d: columns %d..%d of %d filtered (degree %d) t=%.2fs\n", pass, j0,
+                  j0 + nc, q, kq, rclock.s());
+        }
       }
       refine_bapps += (int64_t)(kq + (nullf ? 1 : 0)) * q;
       // drop columns that the null factor has (numerically) annihilated, then

@@ -277,6 +277,8 @@ int choose_degree(double a, double b, double lmin, double lmax, double guard, in
 double cheb_eval(const double* mu, int m, double t);
 
 void spectrum_bounds(const nm_pencil* P, int steps, uint64_t seed, hipStream_t st, double* lmin, double* lmax);
+// rigorous upper bound of the Cowling pencil's spectrum (Gershgorin on D^{-1/2} A D^{-1/2}, element bounds)
+double lmax_rigorous(const nm_pencil* P, hipStream_t st);
 // Filter applications of several concurrent solves on one pencil, batched
 // into one block (columns concatenated, one Chebyshev series per column):
 // every solve thread submits its block and waits; the submission that

@@ -476,14 +476,14 @@ __device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_
 // bound the step through the texture-address unit) drops by the ratio of
 // the rows' entries to the size of their union.  Union columns and
 // coefficients of the workgroup's groups are staged in LDS.
-template <class T, int V, int R, int U = 4>
+template <class T, int V, int R, int U = 4, int GC = 0>
 __global__ __launch_bounds__(256) void k_cj_group(
     uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
     const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
     const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
     T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
     T* Yacc) {
-  constexpr int GCAP = sizeof(T) == 8 ? 640 : 1280;  // about 23-26 KB of LDS either way
+  constexpr int GCAP = GC > 0 ? GC : (sizeof(T) == 8 ? 640 : 1280);  // about 23-26 KB of LDS either way
   __shared__ int32_t s_col[GCAP];
   __shared__ T s_cf[GCAP * R];
   const uint32_t wl = w / V;
@@ -1017,20 +1017,31 @@ void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const
   hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,     \
                      tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,  \
                      cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
+  // experiment switches for the 4-wide step: gathers in flight per lane (4 or
+  // 8) and the LDS stage (1280 union entries, or 896 for 8 workgroups per CU)
   static const int unroll = [] {
-    const char* u = std::getenv("NM_GROUP_UNROLL");  // gathers in flight per lane (4 or 8)
+    const char* u = std::getenv("NM_GROUP_UNROLL");
     return u && std::atoi(u) == 8 ? 8 : 4;
   }();
+  static const int stage = [] {
+    const char* u = std::getenv("NM_GROUP_LDS");
+    return u && std::atoi(u) == 896 ? 896 : 0;
+  }();
+#define NM_GRPX(UU, GG)                                                                                             \
+  hipLaunchKernelGGL((k_cj_group<T, 4, 4, UU, GG>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N,           \
+                     (uint32_t)w, tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, \
+                     wprev, a1, cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
   if (tp.R == 8) {
     if (v == 4) NM_GRP(4, 8); else if (v == 2) NM_GRP(2, 8); else NM_GRP(1, 8);
-  } else if (unroll == 8 && v == 4) {
-    hipLaunchKernelGGL((k_cj_group<T, 4, 4, 8>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,
-                       tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,
-                       cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc);
+  } else if (v == 4 && (unroll == 8 || stage)) {
+    if (unroll == 8 && stage) NM_GRPX(8, 896);
+    else if (unroll == 8) NM_GRPX(8, 0);
+    else NM_GRPX(4, 896);
   } else {
     if (v == 4) NM_GRP(4, 4); else if (v == 2) NM_GRP(2, 4); else NM_GRP(1, 4);
   }
 #undef NM_GRP
+#undef NM_GRPX
 }
 
 // Chebyshev-Jacobi step of the displacement mass solve: LDS tiles where

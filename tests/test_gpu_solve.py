@@ -247,3 +247,27 @@ def test_blow_up_restarts_with_a_larger_bound():
     w, _ = S.dense_window(O.AG.toarray(), O.M.toarray(), 0.5, 40.0)
     assert r.count == 30 and r.stats["lmax"] > 1000.0
     assert np.abs(r.lam - w[:30]).max() <= 1e-10 * w[29]
+
+
+@pytest.mark.parametrize("case", ["ball", "layered"])
+def test_rigorous_spectrum_bound(case):
+    """The Gershgorin bound of nm_spectrum_bound_rigorous lies above every
+    eigenvalue of the pencil (the oracle's dense solve) and within a small
+    factor of the largest; the Lanczos estimate lies between them."""
+    import scipy.linalg as sla
+    import paper_1906_11082_amd as nm
+    if case == "ball":
+        d = make_planet("homogeneous_ball", n_half=3, order=2)
+    else:
+        d = make_planet("three_layer_planet", n_half=3, order=2, pres_order=1)
+    G = nm.Pencil(d)
+    O = OPencil(d)
+    A = O.cowling_dense() if O.n_p else O.AG.toarray()
+    lam_max = sla.eigh(A, O.M.toarray(), eigvals_only=True)[-1]
+    bound = G.spectrum_bound_rigorous()
+    lo, est = G.spectrum_bounds(80, 3)
+    print("%s: lambda_max %.6g, Lanczos estimate %.6g, rigorous bound %.6g (x%.2f)"
+          % (case, lam_max, est, bound, bound / lam_max), flush=True)
+    assert bound >= lam_max * (1 - 1e-12)
+    assert bound <= 20 * lam_max
+    assert lam_max * (1 - 1e-6) <= est <= bound
