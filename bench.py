@@ -80,11 +80,12 @@ def measured_traffic(kernel, leg, block, n_half):
 
 
 def hot_kernel_name(st, leg):
-    """The template instance of the mass-solve step the leg ran (rows of 3 x 32
-    columns: 4 floats or 2 doubles per lane, 4-row groups)."""
+    """The template instance of the mass-solve step the leg ran, as the profiler
+    names it (rows of 3 x 32 columns: 4 floats or 2 doubles per lane, 4-row
+    groups, 4 gathers in flight, the default LDS stage)."""
     if st.get("hot_kernel") != "row-group":
         return None
-    return "k_cj_group<float, 4, 4>" if leg in ("mixed", "fp32") else "k_cj_group<double, 2, 4>"
+    return "k_cj_group<float, 4, 4, 4, 0>" if leg in ("mixed", "fp32") else "k_cj_group<double, 2, 4, 4, 0>"
 
 
 def log(msg):

@@ -483,7 +483,9 @@ __global__ __launch_bounds__(256) void k_cj_group(
     const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
     T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
     T* Yacc) {
-  constexpr int GCAP = GC > 0 ? GC : (sizeof(T) == 8 ? 640 : 1280);  // about 23-26 KB of LDS either way
+  // LDS stage: 640 union entries in FP64 (23 KB), 896 in FP32 (18 KB, so 8
+  // workgroups fit a CU; measured 3 % faster than 1280 at C2, 32 columns)
+  constexpr int GCAP = GC > 0 ? GC : (sizeof(T) == 8 ? 640 : 896);
   __shared__ int32_t s_col[GCAP];
   __shared__ T s_cf[GCAP * R];
   const uint32_t wl = w / V;
@@ -926,7 +928,7 @@ struct GroupPlan {
 };
 // By default only for blocks of at least 32 columns: narrower rows put more
 // groups in a workgroup than its LDS stage holds (640 union entries in FP64,
-// 1280 in FP32).  FP32 at 32 columns on the 384k-tet planet: 0.353 vs
+// 896 in FP32).  FP32 at 32 columns on the 384k-tet planet: 0.343 vs
 // 0.422 ms (grouped vs per-row).  grouped == 2 forces the grouped kernel at
 // any width.
 template <class T>
@@ -1017,31 +1019,12 @@ void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const
   hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,     \
                      tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,  \
                      cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
-  // experiment switches for the 4-wide step: gathers in flight per lane (4 or
-  // 8) and the LDS stage (1280 union entries, or 896 for 8 workgroups per CU)
-  static const int unroll = [] {
-    const char* u = std::getenv("NM_GROUP_UNROLL");
-    return u && std::atoi(u) == 8 ? 8 : 4;
-  }();
-  static const int stage = [] {
-    const char* u = std::getenv("NM_GROUP_LDS");
-    return u && std::atoi(u) == 896 ? 896 : 0;
-  }();
-#define NM_GRPX(UU, GG)                                                                                             \
-  hipLaunchKernelGGL((k_cj_group<T, 4, 4, UU, GG>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N,           \
-                     (uint32_t)w, tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, \
-                     wprev, a1, cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
   if (tp.R == 8) {
     if (v == 4) NM_GRP(4, 8); else if (v == 2) NM_GRP(2, 8); else NM_GRP(1, 8);
-  } else if (v == 4 && (unroll == 8 || stage)) {
-    if (unroll == 8 && stage) NM_GRPX(8, 896);
-    else if (unroll == 8) NM_GRPX(8, 0);
-    else NM_GRPX(4, 896);
   } else {
     if (v == 4) NM_GRP(4, 4); else if (v == 2) NM_GRP(2, 4); else NM_GRP(1, 4);
   }
 #undef NM_GRP
-#undef NM_GRPX
 }
 
 // Chebyshev-Jacobi step of the displacement mass solve: LDS tiles where
