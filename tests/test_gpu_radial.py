@@ -41,3 +41,49 @@ def test_full_size_planet_converges_to_radial_oracle():
         assert b < a / 2.5
         start += m
     assert e12.max() <= 0.02
+
+
+def test_self_gravitating_ball_converges_to_radial_oracle():
+    """The paper's homogeneous test ball (rho 5.51 g/cm^3, V_P 10 km/s, V_S
+    5.7735 km/s, radius 6371 km; nondimensional units) with self-gravitation
+    as N-body sums on the GPU (P2, n_half 4 and 8): the window [0.5, 8] holds
+    as many eigenvalues as the radial oracle's full-gravity multiplets stand
+    for (0T2, 0S2, 1S1: the Cowling l = 1 mode is gone, its place taken by
+    the rigid translations below the window), each multiplet closer to its
+    radial value at n_half 8 than at 4, within 0.6 %.  The frequencies are
+    printed in mHz next to the paper's 1-D values."""
+    import math
+    import planetgen as pg
+    import paper_1906_11082_amd as nm
+    from oracle import radial as RD
+    G, rho0, R = 6.674e-11, 5.51e3, 6371e3
+    T = 1.0 / math.sqrt(math.pi * G * rho0)
+    vp, vs = 10.0e3 * T / R, 5.7735e3 * T / R
+    model = pg.RadialModel(radii=[1.0], rho=[[1.0]], vp=[[vp]], vs=[[vs]], fluid=[False])
+    rows = RD.spectrum([RD.Layer(0, 1, 1.0, vp, vs, False)], 0.5, 8.0, 6, nel=30, p=3, gravity="full")
+    ms = RD.multiset(rows)
+    mhz = lambda w2: math.sqrt(w2) / (2 * math.pi * T) * 1e3
+    paper = {(2, 1): 0.3607, (2, 0): 0.4087, (1, 0): 0.4456}   # 0T2, 0S2, 1S1 (1-D row of the paper's tables)
+    errs = {}
+    for nh in (4, 8):
+        xyz, tet, layer = pg.cubed_ball(nh, [(nh, 1.0)], 1906, 0.1)
+        d = pg._materials(model, xyz, tet, layer, 1906, 0.0, 2, True)
+        d.update(disp_order=2, pres_order=1, omega=(0.0, 0.0, 0.0))
+        print("\n[case] self-gravitating ball n_half %d (%d tets)" % (nh, len(tet)), flush=True)
+        P = nm.Pencil(d)
+        sg = nm.SelfGravity(P, d)
+        sg.attach()
+        r = P.filtered_eig(0.5, 8.0, 40, 1e-8, block=8)
+        print("count %d (radial %d), residual max %.2e" % (r.count, len(ms), r.resid.max()), flush=True)
+        assert r.count == len(ms)
+        assert r.resid.max() <= 1e-8
+        start, e = 0, []
+        for wr, l, kind in rows:
+            m = int(2 * l + 1)
+            mean = r.lam[start:start + m].mean()
+            e.append(abs(mean - wr) / wr)
+            print("  %s l=%d: radial %.4f mHz (paper %.4f), n_half %d %.4f mHz"
+                  % ("ST"[int(kind)], l, mhz(wr), paper[(int(l), int(kind))], nh, mhz(mean)), flush=True)
+            start += m
+        errs[nh] = np.array(e)
+    assert np.all(errs[8] < errs[4]) and errs[8].max() <= 0.006
