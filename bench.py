@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--quiet", action="store_true", help="no per-block solver lines on stderr")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU sharding is "
+        print("bench.py: this program runs on one GPU; --gpus %d is not supported (the multi-GPU sharding is "
               "described in the design notes, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
