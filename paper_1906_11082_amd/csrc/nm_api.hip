@@ -178,7 +178,7 @@ nm_status nm_pencil_export_csr(const nm_pencil* p, int32_t which, int64_t* nrows
       }
       return NM_OK;
     }
-    // displacement rows are stored in the internal (Morton) node order:
+    // displacement rows are stored in the internal (Hilbert) node order:
     // canonical row c is internal row perm[c], internal column j is
     // canonical column iperm[j]; entries are re-sorted by canonical column
     auto perm = d2h(p->perm.p, N);

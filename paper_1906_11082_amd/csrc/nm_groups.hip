@@ -1,12 +1,12 @@
 // Row groups of the node graph for the grouped mass-solve kernel.
 //
-// Rows (displacement nodes, in the internal Morton order) are grouped by R
+// Rows (displacement nodes, in the internal Hilbert-curve order) are grouped by R
 // consecutive rows.  For each group we store the sorted distinct columns
 // its rows touch (the union of their patterns) and an R-wide coefficient
 // row of M_s per union column (zero where a row lacks the column).  The
 // kernel gathers each union column once for all R rows: for the P2 node
-// graph in Morton order a group of 4 rows has ~1.7x fewer union columns
-// than nonzeros (8 rows: ~2.3x, at the price of twice the coefficients).
+// graph in that order a group of 4 rows has ~1.8x fewer union columns
+// than nonzeros (8 rows: ~2.5x, at the price of twice the coefficients).
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -141,7 +141,9 @@ void build_row_groups(nm_pencil* P, hipStream_t st) {
     ptr[t + 1] = ptr[t] + h[t];
   }
   NM_REQUIRE((int64_t)ptr[ng] * R < INT32_MAX, NM_EINVAL, "row groups too large");
-  DBuf<int32_t> gptr(ng + 1), gcol(std::max<int32_t>(ptr[ng], 1));
+  // the union list is padded by 4 entries: the grouped kernel stages it in
+  // 16-byte pieces from a 4-entry boundary
+  DBuf<int32_t> gptr(ng + 1), gcol((size_t)ptr[ng] + 4);
   DBuf<uint16_t> lcol(std::max<int64_t>(P->nnzb, 1));
   NM_HIP(hipMemcpyAsync(gptr.p, ptr.data(), 4 * (ng + 1), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_group_union, dim3((unsigned)ng), dim3(256), 0, st, N, R, P->row_ptr.p, P->col.p, 1, nullptr,
@@ -158,7 +160,7 @@ void build_row_groups(nm_pencil* P, hipStream_t st) {
 }
 
 // LDS tiles for the tiled mass-solve kernel: tiles of TR consecutive rows of
-// the Morton order, the sorted union of their columns (each gathered once
+// the internal order, the sorted union of their columns (each gathered once
 // per tile into LDS) and the union position of every nonzero.  TR = rows, or
 // (rows 0) NM_TILE_ROWS (default 32); with rows 0 the tiles are built only
 // when NM_TILES=1.

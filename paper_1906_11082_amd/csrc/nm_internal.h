@@ -144,7 +144,7 @@ struct nm_pencil {
   // FP32 shadows (built on first use)
   nm::DBuf<float> ag32, ms32, mdinv32, kp32, kpdinv32, eg_val32, egt_val32;
   // numbering (device): canonical node -> geometric node; canonical <-> internal
-  // (Morton) order of the displacement nodes: internal = perm[canonical],
+  // (Hilbert-curve) order of the displacement nodes: internal = perm[canonical],
   // canonical = iperm[internal]
   nm::DBuf<int32_t> node_geom, pres_geom, perm, iperm;
   // row groups of the node graph (grouped mass solve): grp_rows 0 -> per-row kernel

@@ -439,27 +439,35 @@ __global__ __launch_bounds__(256) void k_cj_step(uint32_t rows, uint32_t w, cons
 
 
 // sum over the group's union columns of coef[., r] X[col] for the R rows;
-// cl / cf as in row_spmv (LDS or global arrays, entry l at l - base)
+// cl / cf as in row_spmv (LDS or global arrays): column entry l at
+// cl[l - cbase], its R coefficients at cf[(l - fbase) R].  Entries past the
+// group's end read entry l0 again (in range) with the coefficients scaled
+// by 0, so every load is unconditional.
 template <class T, int V, int R, int U = 4>
-__device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_t base, int32_t l0, int32_t l1,
-                                          const T* __restrict__ X, uint32_t w, uint32_t e, Vx<T, V> (&acc)[R]) {
+__device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_t cbase, int32_t fbase, int32_t l0,
+                                          int32_t l1, const T* __restrict__ X, uint32_t w, uint32_t e,
+                                          Vx<T, V> (&acc)[R]) {
   for (int32_t l = l0; l < l1; l += U) {
+    int32_t li[U];
     uint32_t c[U];
-    bool in[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      in[u] = l + u < l1;
-      c[u] = (uint32_t)cl[(in[u] ? l + u : l0) - base];
+      li[u] = l + u < l1 ? l + u : l0;
+      c[u] = (uint32_t)cl[li[u] - cbase];
     }
     Vx<T, V> x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(X + (size_t)(c[u] * w + e));
+    for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(X + ((size_t)c[u] * w + e));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const T* a = cf + (size_t)((in[u] ? l + u : l0) - base) * R;
+      const T* a = cf + (size_t)(li[u] - fbase) * R;
+      T av[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) av[r] = a[r];
+      const T keep = l + u < l1 ? T(1) : T(0);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T ar = in[u] ? a[r] : T(0);
+        const T ar = av[r] * keep;
 #pragma unroll
         for (int i = 0; i < V; ++i) acc[r].v[i] += ar * x[u].v[i];
       }
@@ -468,7 +476,7 @@ __device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_
 }
 
 // Row-group Chebyshev-Jacobi step (same arithmetic and modes as k_cj_step).
-// Rows are processed in groups of R consecutive rows of the Morton order;
+// Rows are processed in groups of R consecutive rows of the internal order;
 // each lane owns one V-wide entry slot of all R rows and walks the union of
 // their columns once, with an R-wide coefficient row per union column
 // (zeros where a row lacks the column).  A gathered neighbour row serves
@@ -477,27 +485,39 @@ __device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_
 // the rows' entries to the size of their union.  Union columns and
 // coefficients of the workgroup's groups are staged in LDS.
 template <class T, int V, int R, int U = 4, int GC = 0>
-__global__ __launch_bounds__(256) void k_cj_group(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cj_group(
     uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
     const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
     const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
     T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
     T* Yacc) {
   // LDS stage: 640 union entries in FP64 (23 KB), 896 in FP32 (18 KB, so 8
-  // workgroups fit a CU; measured 3 % faster than 1280 at C2, 32 columns)
+  // workgroups fit a CU; measured 3 % faster than 1280 at C2, 32 columns).
+  // The waves-per-SIMD hint asks for at most 64 VGPRs, which the FP32 4-row
+  // kernel at 16-byte rows meets without spilling (8 waves per SIMD, as
+  // many as the LDS stage allows)
   constexpr int GCAP = GC > 0 ? GC : (sizeof(T) == 8 ? 640 : 896);
-  __shared__ int32_t s_col[GCAP];
-  __shared__ T s_cf[GCAP * R];
+  static_assert(GCAP % 4 == 0 && (R * sizeof(T)) % 16 == 0, "16-byte LDS staging");
+  __shared__ __align__(16) int32_t s_col[GCAP];
+  __shared__ __align__(16) T s_cf[GCAP * R];
   const uint32_t wl = w / V;
   const uint32_t ngroups = (N + R - 1) / R;
   const uint32_t g = lane_id();
   const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
   const uint32_t G0 = min(g0 / wl, ngroups - 1), G1 = min((g0 + blockDim.x - 1) / wl, ngroups - 1);
   const int32_t lb = gptr[G0], le = gptr[G1 + 1];
-  const bool staged = le - lb <= GCAP;
+  // columns staged from lb rounded down to 4 entries (the union list is
+  // padded by 4 entries at its end), coefficients from lb: both copied in
+  // 16-byte pieces
+  const int32_t cb = lb & ~3;
+  const bool staged = le - cb <= GCAP;
   if (staged) {
-    for (int32_t i = threadIdx.x; i < le - lb; i += blockDim.x) s_col[i] = gcol[lb + i];
-    for (int32_t i = threadIdx.x; i < (le - lb) * R; i += blockDim.x) s_cf[i] = gcoef[(size_t)lb * R + i];
+    const int32_t nc = (le - cb + 3) >> 2;
+    const int4* sc = reinterpret_cast<const int4*>(gcol + cb);
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) reinterpret_cast<int4*>(s_col)[i] = sc[i];
+    const int32_t nq = (int32_t)((size_t)(le - lb) * R * sizeof(T) / 16);
+    const int4* sf = reinterpret_cast<const int4*>(gcoef + (size_t)lb * R);
+    for (int32_t i = threadIdx.x; i < nq; i += blockDim.x) reinterpret_cast<int4*>(s_cf)[i] = sf[i];
   }
   __syncthreads();
   if (g >= ngroups * wl) return;
@@ -510,9 +530,9 @@ __global__ __launch_bounds__(256) void k_cj_group(
     for (int i = 0; i < V; ++i) acc[r].v[i] = T(0);
   const int32_t l0 = gptr[grp], l1 = gptr[grp + 1];
   if (staged)
-    group_sum<T, V, R, U>(s_col, s_cf, lb, l0, l1, ycur, w, e, acc);
+    group_sum<T, V, R, U>(s_col, s_cf, cb, lb, l0, l1, ycur, w, e, acc);
   else
-    group_sum<T, V, R, U>(gcol, gcoef, 0, l0, l1, ycur, w, e, acc);
+    group_sum<T, V, R, U>(gcol, gcoef, 0, 0, l0, l1, ycur, w, e, acc);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t row = r0 + r;
@@ -564,7 +584,7 @@ __global__ __launch_bounds__(256) void k_cj_group(
 
 // LDS-tiled Chebyshev-Jacobi step (same arithmetic, modes and summation
 // order as k_cj_step, so the results are bit-identical).  A workgroup owns
-// one tile of TR = 256 / LPR consecutive Morton rows and one chunk of
+// one tile of TR = 256 / LPR consecutive internal rows and one chunk of
 // C = LPR * V consecutive entries of the row width w (V entries = 16 bytes
 // per lane); each group of LPR lanes owns one row of the tile:
 //   0. the own row's stream operands (f, y_prev, y, and the filter's) are

@@ -181,7 +181,7 @@ def test_assembly_is_deterministic(torch_cuda):
 
 @pytest.mark.parametrize("ncols", [3, 8, 16, 32])
 def test_row_group_kernel_matches_per_row(torch_cuda, ncols, monkeypatch):
-    """The row-group mass-solve kernel (4 or 8 Morton rows per lane, union
+    """The row-group mass-solve kernel (4 or 8 consecutive internal rows per lane, union
     columns with zero-padded coefficients) and the LDS-tile kernel (32 or 64
     rows per tile, 128- or 64-byte row chunks) sum each row in the same
     column order as the per-row kernel: FP64 and FP32 results are
