@@ -509,6 +509,33 @@ nm_status nm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx)
  * allocating or launching anything.  Host-only; NM_EINVAL if n_disp <= 0. */
 nm_status nm_max_block_columns(int64_t n_disp, int64_t* max_cols);
 
+/* Dense block products of the filtered Lanczos (Sec. 6.2: the Gram-Schmidt
+ * projections of a new block against the basis, the Gram matrices of its
+ * Cholesky orthonormalisation and the Rayleigh-Ritz matrices V^T A V), on the
+ * FP64 matrix cores — the kernels the solver uses, for callers that build or
+ * orthogonalise their own blocks.  All matrices are FP64 device memory owned
+ * by the caller; work is enqueued on `stream` (NULL: the default stream).
+ *
+ * nm_gemm_tn: C = A^T B, K x q, column-major with leading dimension K; A is
+ * row-major [n][lda] (its first K columns are used, lda >= K), B row-major
+ * [n][ldb] (first q columns, ldb >= q).  The rows are summed in fixed chunks
+ * whose partial products are added in chunk order (the result does not
+ * depend on scheduling); the partials (n-dependent, at most about
+ * 4096 / ceil(K/64) / ceil(q/64) chunks of K x q) are allocated for the call,
+ * which synchronises the stream before it returns.  n = 0 gives C = 0.
+ *
+ * nm_gemm_nn: D = alpha A C + beta D; A row-major [n][lda] (first K columns),
+ * C column-major K x q with leading dimension ldc >= K, D row-major [n][ldd]
+ * (first q columns, ldd >= q; not read when beta is 0); A and D must not be
+ * the same array.  Asynchronous, allocates nothing.
+ *
+ * NM_EINVAL on negative sizes, leading dimensions below the used widths,
+ * null matrices of a non-empty product, or A == D. */
+nm_status nm_gemm_tn(int64_t n, int32_t K, int32_t q, const double* A, int32_t lda, const double* B, int32_t ldb,
+                     double* C, void* stream);
+nm_status nm_gemm_nn(int64_t n, int32_t K, int32_t q, double alpha, const double* A, int32_t lda, const double* C,
+                     int32_t ldc, double beta, double* D, int32_t ldd, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* nm_last_error(void);
 

@@ -33,7 +33,7 @@ EXPORTED = ["nm_assemble", "nm_pencil_info_get", "nm_pencil_export_csr", "nm_pen
             "nm_spectrum_dos", "nm_dos_count", "nm_dos_slices", "nm_spectrum_dos_weighted", "nm_dos_count_weighted",
             "nm_dos_slices_weighted", "nm_spectrum_bound_rigorous", "nm_refine_rotation",
             "nm_selfgrav_build", "nm_selfgrav_info", "nm_selfgrav_apply", "nm_selfgrav_field",
-            "nm_pencil_attach_selfgrav", "nm_selfgrav_free"]
+            "nm_pencil_attach_selfgrav", "nm_selfgrav_free", "nm_gemm_tn", "nm_gemm_nn"]
 
 
 class NMError(RuntimeError):
@@ -175,6 +175,9 @@ def load_library(path: str | None = None):
         "nm_dos_count_weighted": ([P, C.c_int32] + [C.c_double] * 4 + [C.POINTER(C.c_double)], C.c_int32),
         "nm_dos_slices_weighted": ([P, C.c_int32] + [C.c_double] * 4 + [C.c_int32, P], C.c_int32),
         "nm_spectrum_bound_rigorous": ([P, P, C.POINTER(C.c_double)], C.c_int32),
+        "nm_gemm_tn": ([C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P, C.c_int32, P, P], C.c_int32),
+        "nm_gemm_nn": ([C.c_int64, C.c_int32, C.c_int32, C.c_double, P, C.c_int32, P, C.c_int32, C.c_double, P,
+                        C.c_int32, P], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -196,6 +199,46 @@ def _stream():
 
 def _ptr(a):
     return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(a.data_ptr())
+
+
+def _rows(a, name):
+    if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.dim() == 2
+            and (a.shape[1] <= 1 or a.stride(1) == 1)):
+        raise ValueError("%s: a 2-D float64 CUDA tensor with contiguous rows" % name)
+    return max(a.stride(0), a.shape[1]) if a.shape[0] <= 1 else a.stride(0)
+
+
+def gemm_tn(A, B, K=None, q=None):
+    """C = A[:, :K]^T B[:, :q] (K x q) through nm_gemm_tn, the solver's block
+    product on the FP64 matrix cores.  A, B: float64 CUDA tensors [n][*] with
+    contiguous rows (leading dimensions from their row strides)."""
+    lib = load_library()
+    lda, ldb = _rows(A, "A"), _rows(B, "B")
+    if A.shape[0] != B.shape[0]:
+        raise ValueError("A and B need the same number of rows")
+    K = A.shape[1] if K is None else K
+    q = B.shape[1] if q is None else q
+    Ct = torch.empty((q, K), dtype=torch.float64, device=A.device)  # column-major K x q
+    _check(lib.nm_gemm_tn(A.shape[0], K, q, _ptr(A), lda, _ptr(B), ldb, _ptr(Ct), _stream()))
+    return Ct.t()
+
+
+def gemm_nn(A, Cm, D=None, alpha=1.0, beta=0.0):
+    """D = alpha A[:, :K] Cm + beta D through nm_gemm_nn (Cm: K x q, any
+    layout; D: [n][q'] float64 CUDA tensor with contiguous rows, q' >= q,
+    created when None).  Returns D."""
+    lib = load_library()
+    lda = _rows(A, "A")
+    K, q = Cm.shape
+    Cc = Cm.detach().to(device=A.device, dtype=torch.float64).t().contiguous()  # column-major K x q
+    if D is None:
+        D = torch.empty((A.shape[0], q), dtype=torch.float64, device=A.device)
+    ldd = _rows(D, "D")
+    if D.shape[0] != A.shape[0] or D.shape[1] < q:
+        raise ValueError("D must be [n][>= q]")
+    _check(lib.nm_gemm_nn(A.shape[0], K, q, float(alpha), _ptr(A), lda, _ptr(Cc), K, float(beta), _ptr(D), ldd,
+                           _stream()))
+    return D
 
 
 def set_allocator(alloc=None, free=None):

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libnmodes.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["nm_ref.cpp", "nm_assemble.hip", "nm_groups.hip", "nm_ops.hip", "nm_eig.hip", "nm_slices.hip",
            "nm_rotation.hip", "nm_api.hip", "nm_server.hip", "nm_noalloc.hip",
-           "nm_selfgrav.hip"]
+           "nm_selfgrav.hip", "nm_gemm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -106,6 +106,25 @@ nm_status nm_max_block_columns(int64_t n_disp, int64_t* max_cols) {
   })
 }
 
+nm_status nm_gemm_tn(int64_t n, int32_t K, int32_t q, const double* A, int32_t lda, const double* B, int32_t ldb,
+                     double* C, void* stream) {
+  NM_TRY({
+    NM_REQUIRE((int64_t)K * q <= 0 || (C && (n <= 0 || (A && B))), NM_EINVAL, "null matrix");
+    nm::DBuf<double> ws;
+    const hipStream_t st = (hipStream_t)stream;
+    nm::gemm_tn(n, K, q, A, lda, B, ldb, C, ws, st);
+    NM_HIP(hipStreamSynchronize(st));  // the partials are freed on return
+  })
+}
+
+nm_status nm_gemm_nn(int64_t n, int32_t K, int32_t q, double alpha, const double* A, int32_t lda, const double* Cm,
+                     int32_t ldc, double beta, double* D, int32_t ldd, void* stream) {
+  NM_TRY({
+    NM_REQUIRE(n <= 0 || q <= 0 || (D && (K <= 0 || (A && Cm))), NM_EINVAL, "null matrix");
+    nm::gemm_nn(n, K, q, alpha, A, lda, Cm, ldc, beta, D, ldd, (hipStream_t)stream);
+  })
+}
+
 nm_status nm_assemble(const nm_mesh* mesh, const nm_material* mat, const double omega[3], void* stream,
                       nm_pencil** out) {
   NM_TRY({

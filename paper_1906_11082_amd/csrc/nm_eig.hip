@@ -171,19 +171,18 @@ __global__ void k_scale_cols(int64_t rows, int nc, const double* __restrict__ s,
 }
 
 struct Blas {
-  rocblas_handle h;
-  // row-major helpers expressed through column-major GEMM
+  rocblas_handle h;  // small dense products (k x k) and the dense eigensolver
+  hipStream_t st;
+  DBuf<double> ws;  // row-chunk partial products of tn
+  // row-major helpers on the FP64 matrix cores (nm_gemm.hip)
   // C[K][q] (col-major K x q, ld K) = A^T B, A row-major [n][*] (ld lda, first K cols), B row-major [n][*] (q cols)
-  void tn(int64_t n, int K, int q, const double* A, int lda, const double* B, int ldb, double* C, double alpha = 1.0,
-          double beta = 0.0) {
-    NM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, q, (rocblas_int)n, &alpha, A,
-                          lda, B, ldb, &beta, C, K));
+  void tn(int64_t n, int K, int q, const double* A, int lda, const double* B, int ldb, double* C) {
+    gemm_tn(n, K, q, A, lda, B, ldb, C, ws, st);
   }
   // D (row-major [n][q], ld ldd) = alpha * A (row-major [n][K], ld lda) * C (col-major K x q, ld ldc) + beta * D
   void nn(int64_t n, int K, int q, double alpha, const double* A, int lda, const double* C, int ldc, double beta,
           double* D, int ldd) {
-    NM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, q, (rocblas_int)n, K, &alpha, C,
-                          ldc, A, lda, &beta, D, ldd));
+    gemm_nn(n, K, q, alpha, A, lda, C, ldc, beta, D, ldd, st);
   }
 };
 
@@ -314,7 +313,7 @@ void spectrum_bounds(const nm_pencil* P, int steps_req, uint64_t seed, hipStream
   const int64_t n = 3 * P->N;
   const int steps = (int)std::min<int64_t>(steps_req, n - 1);
   NM_REQUIRE(steps >= 2, NM_EINVAL, "problem too small for spectrum bounds");
-  Blas bl{P->blas};
+  Blas bl{P->blas, st, {}};
   NM_BLAS(rocblas_set_stream(bl.h, st));
   NM_BLAS(rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host));
   ApplyCfg bc;
@@ -446,7 +445,7 @@ static void filtered_eig_once(const nm_pencil* P, double a, double b, int nev, d
   cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, ptol);
   cfg.precision = prec;
   set_mass_passes(const_cast<nm_pencil*>(P), cfg, o.mass_passes, mtol, 0, st);
-  Blas bl{blas ? blas : P->blas};
+  Blas bl{blas ? blas : P->blas, st, {}};
   NM_BLAS(rocblas_set_stream(bl.h, st));
   NM_BLAS(rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host));
 

@@ -210,6 +210,13 @@ int mass_kernel_kind(const nm_pencil* P, int b, bool fp32);
 void set_mass_passes(nm_pencil* P, ApplyCfg& cfg, int passes, double mtol, int kM_pass, hipStream_t st);
 // fastest block width and mass-solve kernel for this pencil (sets tuned_block and grouped)
 void autotune(nm_pencil* P, int precision, hipStream_t st, int* best_b, double* best_us_per_col);
+// dense block products on the FP64 matrix cores (nm_gemm.hip):
+// C (col-major K x q) = A^T B with A [n][lda], B [n][ldb] row-major; ws: row-chunk partials
+void gemm_tn(int64_t n, int K, int q, const double* A, int lda, const double* B, int ldb, double* C, DBuf<double>& ws,
+             hipStream_t st);
+// D ([n][ldd] row-major) = alpha A C + beta D with A [n][lda] row-major, C col-major K x q (ld ldc)
+void gemm_nn(int64_t n, int K, int q, double alpha, const double* A, int lda, const double* C, int ldc, double beta,
+             double* D, int ldd, hipStream_t st);
 // work buffers of apply_op_ws for op on b columns: nvec vectors of `vec` elements,
 // then npres vectors of `pres` elements (elements of the operator's precision)
 struct OpWorkElems {

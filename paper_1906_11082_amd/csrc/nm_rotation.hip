@@ -137,10 +137,9 @@ void project_core(const nm_pencil* P, const nm_eig_result* B, double a, double b
   DBuf<double> RX((size_t)n * m), Sd((size_t)m * m);
   ApplyCfg cfg;
   api_apply(P, NM_OP_R, m, B->X, RX.p, cfg, st);
-  const double one = 1.0, zero = 0.0;
   // S (col-major m x m) = X^T R X
-  NM_BLAS(rocblas_dgemm(P->blas, rocblas_operation_none, rocblas_operation_transpose, m, m, (rocblas_int)n, &one,
-                        B->X, m, RX.p, m, &zero, Sd.p, m));
+  DBuf<double> ws;
+  gemm_tn(n, m, m, B->X, m, RX.p, m, Sd.p, ws, st);
   std::vector<double> S((size_t)m * m);
   NM_HIP(hipMemcpyAsync(S.data(), Sd.p, 8 * S.size(), hipMemcpyDeviceToHost, st));
   NM_HIP(hipStreamSynchronize(st));
@@ -204,10 +203,8 @@ void project_core(const nm_pencil* P, const nm_eig_result* B, double a, double b
     NM_HIP(hipMemcpyAsync(Yrd.p, Yr.data(), 8 * Yr.size(), hipMemcpyHostToDevice, st));
     NM_HIP(hipMemcpyAsync(Yid.p, Yi.data(), 8 * Yi.size(), hipMemcpyHostToDevice, st));
     // U (row-major [n][k]) = X Y : U^T = Y^T X^T
-    NM_BLAS(rocblas_dgemm(P->blas, rocblas_operation_transpose, rocblas_operation_none, k, (rocblas_int)n, m, &one,
-                          Yrd.p, m, B->X, m, &zero, Ur.p, k));
-    NM_BLAS(rocblas_dgemm(P->blas, rocblas_operation_transpose, rocblas_operation_none, k, (rocblas_int)n, m, &one,
-                          Yid.p, m, B->X, m, &zero, Ui.p, k));
+    gemm_nn(n, m, k, 1.0, B->X, m, Yrd.p, m, 0.0, Ur.p, k, st);
+    gemm_nn(n, m, k, 1.0, B->X, m, Yid.p, m, 0.0, Ui.p, k, st);
     NM_HIP(hipMalloc((void**)&r->U, 16 * (size_t)n * k));
     hipLaunchKernelGGL(k_interleave, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, Ur.p, Ui.p, r->U);
     hipLaunchKernelGGL(k_phase, dim3(k), dim3(256), 0, st, n, k, r->U);
@@ -296,7 +293,7 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
   ApplyCfg cfg;
   cfg.kM = cheb_steps(P->ref.m_lo, P->ref.m_hi, 1e-12);
   cfg.kP = cheb_steps(P->ref.p_lo, P->ref.p_hi, 1e-13);
-  const double one = 1.0, zero = 0.0, mone = -1.0;
+  DBuf<double> ws;  // row-chunk partials of the block products
   // basis V and A V (canonical order, row-major [n][ld]); capacity for every pass's corrections
   const int kmax = R0->count;
   const int ld = m0 + iters * 2 * std::max(kmax, 1) + 2 * std::max(kmax, 1);
@@ -361,16 +358,13 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
     DBuf<double> Cd((size_t)m * nc);
     for (int pass = 0; pass < 2; ++pass) {
       api_apply(P, NM_OP_M, nc, G, RX.p, cfg, st);
-      NM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, m, nc, (rocblas_int)n, &one, V.p,
-                            ld, RX.p, nc, &zero, Cd.p, m));
-      NM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nc, (rocblas_int)n, m, &mone, Cd.p,
-                            m, V.p, ld, &one, G, nc));
+      gemm_tn(n, m, nc, V.p, ld, RX.p, nc, Cd.p, ws, st);
+      gemm_nn(n, m, nc, -1.0, V.p, ld, Cd.p, m, 1.0, G, nc, st);
     }
     // M-orthonormalise G: eigenvectors of its (scaled) Gram matrix, dropping directions below 1e-10
     api_apply(P, NM_OP_M, nc, G, RX.p, cfg, st);
     DBuf<double> Gd((size_t)nc * nc);
-    NM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, nc, nc, (rocblas_int)n, &one, G, nc,
-                          RX.p, nc, &zero, Gd.p, nc));
+    gemm_tn(n, nc, nc, G, nc, RX.p, nc, Gd.p, ws, st);
     std::vector<double> Gh((size_t)nc * nc), gw;
     NM_HIP(hipMemcpyAsync(Gh.data(), Gd.p, 8 * Gh.size(), hipMemcpyDeviceToHost, st));
     NM_HIP(hipStreamSynchronize(st));
@@ -401,8 +395,7 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
         Cm[i + (size_t)c2 * nc] = dsc[i] * Gh[i + (size_t)keep[c2] * nc] / std::sqrt(gw[keep[c2]]);
     DBuf<double> Cmd((size_t)nc * r), Gn((size_t)n * r);
     NM_HIP(hipMemcpyAsync(Cmd.p, Cm.data(), 8 * Cm.size(), hipMemcpyHostToDevice, st));
-    NM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, r, (rocblas_int)n, nc, &one, Cmd.p,
-                          nc, G, nc, &zero, Gn.p, r));
+    gemm_nn(n, nc, r, 1.0, G, nc, Cmd.p, nc, 0.0, Gn.p, r, st);
     NM_HIP(hipMemcpy2DAsync(V.p + m, 8 * (size_t)ld, Gn.p, 8 * (size_t)r, 8 * (size_t)r, n, hipMemcpyDeviceToDevice,
                             st));
     api_apply(P, NM_OP_A, r, Gn.p, MX.p, cfg, st);
@@ -411,8 +404,7 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
     m += r;
     // Rayleigh-Ritz: eigenvectors of K = V^T A V, then the projected problem on them
     DBuf<double> Kd((size_t)m * m);
-    NM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, m, m, (rocblas_int)n, &one, V.p, ld,
-                          AV.p, ld, &zero, Kd.p, m));
+    gemm_tn(n, m, m, V.p, ld, AV.p, ld, Kd.p, ws, st);
     std::vector<double> Kh((size_t)m * m), kw;
     NM_HIP(hipMemcpyAsync(Kh.data(), Kd.p, 8 * Kh.size(), hipMemcpyDeviceToHost, st));
     NM_HIP(hipStreamSynchronize(st));
@@ -436,8 +428,7 @@ void refine_rotation(const nm_pencil* P, const nm_eig_result* B, const nm_rot_re
     }
     DBuf<double> Qd((size_t)m * mk), W((size_t)n * mk);
     NM_HIP(hipMemcpyAsync(Qd.p, Qk.data(), 8 * Qk.size(), hipMemcpyHostToDevice, st));
-    NM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, mk, (rocblas_int)n, m, &one, Qd.p, m,
-                          V.p, ld, &zero, W.p, mk));
+    gemm_nn(n, m, mk, 1.0, V.p, ld, Qd.p, m, 0.0, W.p, mk, st);
     nm_eig_result tmp;
     std::memset(&tmp, 0, sizeof(tmp));
     tmp.count = mk;

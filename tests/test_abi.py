@@ -168,3 +168,20 @@ def test_dos_count_and_slices_match_oracle(lib):
         assert np.abs(e1 - e2).max() <= 1e-7 * b
     with pytest.raises(nm.NMError):
         nm.dos_count(tw, lmin, lmax, 0.0, 10.0, weighted=True)
+
+
+def test_block_products_reject_bad_arguments(lib):
+    """The dense block products check their sizes on the host before any
+    launch: leading dimensions below the used widths, negative sizes, null
+    matrices of a non-empty product and an output that is the input."""
+    import ctypes as C
+    dummy = C.c_void_p(256)  # never dereferenced: every call below fails its checks first
+    assert lib.nm_gemm_tn(10, 8, 4, dummy, 7, dummy, 4, dummy, None) == -1       # lda < K
+    assert lib.nm_gemm_tn(10, 8, 4, dummy, 8, dummy, 3, dummy, None) == -1       # ldb < q
+    assert lib.nm_gemm_tn(-1, 8, 4, dummy, 8, dummy, 4, dummy, None) == -1       # n < 0
+    assert lib.nm_gemm_tn(10, 8, 4, None, 8, dummy, 4, dummy, None) == -1        # null A
+    assert lib.nm_gemm_nn(10, 8, 4, 1.0, dummy, 8, dummy, 7, 0.0, dummy, 4, None) == -1  # ldc < K
+    assert lib.nm_gemm_nn(10, 8, 4, 1.0, dummy, 8, dummy, 8, 0.0, dummy, 3, None) == -1  # ldd < q
+    assert lib.nm_gemm_nn(10, 8, 4, 1.0, dummy, 8, dummy, 8, 0.0, None, 4, None) == -1   # null D
+    assert lib.nm_gemm_nn(10, 8, 4, 1.0, dummy, 8, C.c_void_p(512), 8, 0.0, dummy, 4, None) == -1  # A == D
+    assert "gemm" in lib.nm_last_error().decode() or "null" in lib.nm_last_error().decode()
