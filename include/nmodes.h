@@ -246,13 +246,18 @@ nm_status nm_pencil_apply_noalloc(const nm_pencil* p, int32_t op, int32_t ncols,
                                   const nm_apply_opts* opts, void* stream);
 
 /* Autotuning of the mass-solve step (the hot loop of every filter step) on
- * this pencil: times middle Chebyshev-Jacobi steps for block widths 8, 16,
- * 32 and 64 and, in FP64, the per-row and row-group kernels, then keeps the
- * fastest per column: nm_filtered_eig with block 0 uses that width (at most
- * nev / 4, rounded down to a multiple of 8, at least 8) and every
- * later mass solve that kernel choice.  Allocates 3 x 64 columns of work
- * vectors for the duration of the call.  block / us_per_column (may be NULL):
- * the winner and its time per column and step in microseconds. */
+ * this pencil, in FP64 (precision 0) or FP32 (1): times middle
+ * Chebyshev-Jacobi steps for block widths 8, 16, 32 and 64 with the per-row
+ * kernel, the row-group kernel at groups of 4 and of 8 rows (the block size
+ * of the grouped format: rows times the union of their columns), and the
+ * LDS-tile kernel at tiles of 32 and 64 rows, then keeps the fastest per
+ * column: nm_filtered_eig with block 0 uses that width (at most nev / 4,
+ * rounded down to a multiple of 8, at least 8) and every later mass solve
+ * that kernel and block size (the row groups and tiles are rebuilt for it).
+ * Allocates 3 x 64 columns of work vectors for the duration of the call; do
+ * not call it while another call uses the pencil.  block / us_per_column
+ * (may be NULL): the winner and its time per column and step in
+ * microseconds. */
 nm_status nm_pencil_autotune(nm_pencil* p, int32_t precision, void* stream, int32_t* block, double* us_per_column);
 
 /* Jackson-damped Chebyshev coefficients mu[0..m] of the indicator of [a, b]

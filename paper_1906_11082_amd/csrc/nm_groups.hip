@@ -113,16 +113,18 @@ __global__ void k_group_coef(int64_t N, int R, const int32_t* __restrict__ rp, c
   for (int32_t k = rp[row]; k < rp[row + 1]; ++k) coef[((int64_t)gptr[g] + lcol[k]) * R + r] = val[k];
 }
 
-void build_row_groups(nm_pencil* P, hipStream_t st) {
-  // NM_ROW_GROUPS: 0 per-row kernel only, 1 (default) grouped from 32 columns, 2 grouped at any width
-  const char* env = getenv("NM_ROW_GROUPS");
-  P->grouped = env ? atoi(env) : 1;
-  if (P->grouped <= 0) {
-    P->grouped = 0;
-    return;
+void build_row_groups(nm_pencil* P, hipStream_t st, int rows) {
+  if (rows <= 0) {
+    // NM_ROW_GROUPS: 0 per-row kernel only, 1 (default) grouped from 32 columns, 2 grouped at any width
+    const char* env = getenv("NM_ROW_GROUPS");
+    P->grouped = env ? atoi(env) : 1;
+    if (P->grouped <= 0) {
+      P->grouped = 0;
+      return;
+    }
   }
   const char* renv = getenv("NM_GROUP_ROWS");
-  const int R = renv ? atoi(renv) : 4;
+  const int R = rows > 0 ? rows : (renv ? atoi(renv) : 4);
   NM_REQUIRE(R == 4 || R == 8, NM_EINVAL, "row groups of 4 or 8 rows");
   const int64_t N = P->N;
   const int64_t ng = (N + R - 1) / R;
@@ -157,6 +159,12 @@ void build_row_groups(nm_pencil* P, hipStream_t st) {
   P->grp_ptr = std::move(gptr);
   P->grp_col = std::move(gcol);
   P->grp_coef = std::move(coef);
+  if (P->ms32.p) {
+    // the FP32 shadows exist already: give the new coefficients theirs
+    P->grp_coef32.alloc(std::max<size_t>(P->grp_coef.n, 1));
+    convert_f64_f32((int64_t)P->grp_coef.n, P->grp_coef.p, P->grp_coef32.p, st);
+    NM_HIP(hipStreamSynchronize(st));
+  }
 }
 
 // LDS tiles for the tiled mass-solve kernel: tiles of TR consecutive rows of

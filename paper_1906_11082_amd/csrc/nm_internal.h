@@ -173,7 +173,8 @@ namespace nm {
 // pattern + assembly (nm_assemble.hip)
 void assemble(nm_pencil* P, const nm_mesh* mesh, const nm_material* mat, hipStream_t st);
 // row groups and LDS tiles (nm_groups.hip)
-void build_row_groups(nm_pencil* P, hipStream_t st);
+// rows 0: from the environment (NM_ROW_GROUPS, NM_GROUP_ROWS; default 4), else groups of `rows` (4 or 8)
+void build_row_groups(nm_pencil* P, hipStream_t st, int rows = 0);
 // tiles of `rows` rows (0: NM_TILE_ROWS or 32, and NM_TILES=0 switches them off)
 void build_tiles(nm_pencil* P, hipStream_t st, int rows = 0);
 

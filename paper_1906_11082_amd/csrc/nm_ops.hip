@@ -1527,14 +1527,19 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
   NM_HIP(hipEventCreate(&e0));
   NM_HIP(hipEventCreate(&e1));
   double best = 1e300;
-  int bb = 16, bgrp = P->grouped, btile = 0;
-  // candidate kernels: (tile rows, grouped mode); tile rows 0 = no tiles
+  const int rows0 = P->grp_rows;
+  int bb = 16, bgrp = P->grouped, btile = 0, brows = rows0;
+  // candidate kernels: (tile rows, grouped mode, rows per group); tile rows 0
+  // = no tiles.  The row-group size is the block size of the grouped format
+  // (rows x their column union, zero-padded): larger groups gather fewer
+  // neighbour rows per output row but carry more coefficients and registers.
   struct Cand {
-    int tr, grouped;
+    int tr, grouped, rows;
   };
-  std::vector<Cand> cands = {{0, 0}};
-  if (P->grp_rows > 0) cands.push_back({0, 2});
-  for (int tr : {32, 64}) cands.push_back({tr, 0});
+  std::vector<Cand> cands = {{0, 0, 0}};
+  if (rows0 > 0)
+    for (int r : {4, 8}) cands.push_back({0, 2, r});
+  for (int tr : {32, 64}) cands.push_back({tr, 0, 0});
   const char* venv = getenv("NM_AUTOTUNE_VERBOSE");
   const bool verbose = venv && atoi(venv) != 0;
   for (const Cand& cd : cands) {
@@ -1543,6 +1548,10 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
       if (P->tile_rows != cd.tr) continue;  // this tile size does not fit
     } else {
       P->tiled = 0;
+    }
+    if (cd.rows > 0 && P->grp_rows != cd.rows) {
+      build_row_groups(P, st, cd.rows);
+      if (P->grp_rows != cd.rows) continue;  // a group of this size does not fit the union sort
     }
     P->grouped = cd.grouped;
     for (int b : {8, 16, 32, 64}) {
@@ -1563,14 +1572,16 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
       NM_HIP(hipEventElapsedTime(&ms, e0, e1));
       const double us = 1e3 * ms / reps / b;
       if (verbose)
-        fprintf(stderr, "[autotune] %s b=%d kernel=%s tile_rows=%d: %.1f us per step, %.3f us per column\n",
+        fprintf(stderr,
+                "[autotune] %s b=%d kernel=%s tile_rows=%d group_rows=%d: %.1f us per step, %.3f us per column\n",
                 sizeof(T) == 8 ? "fp64" : "fp32", b, tp.tile.on ? "tile" : (tp.group.on ? "group" : "row"), cd.tr,
-                1e3 * ms / reps, us);
+                tp.group.on ? P->grp_rows : 0, 1e3 * ms / reps, us);
       if (us < best) {
         best = us;
         bb = b;
         bgrp = cd.grouped;
         btile = cd.tr;
+        brows = cd.rows > 0 ? cd.rows : rows0;
       }
     }
   }
@@ -1581,6 +1592,7 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
   } else {
     P->tiled = 0;
   }
+  if (brows > 0 && P->grp_rows != brows) build_row_groups(P, st, brows);
   P->grouped = bgrp;
   P->tuned_block = bb;
   P->tuned_tile = btile;

@@ -216,6 +216,34 @@ def test_autotune_picks_a_block_and_solves():
     assert np.abs(r.lam - ref.lam).max() <= 1e-9 * ref.lam.max()
 
 
+def test_autotune_times_group_sizes_and_keeps_fp32_coefficients(capfd, monkeypatch):
+    """The FP32 autotuner also times row groups of 4 and 8 rows (the block
+    size of the grouped format), rebuilding the groups and their FP32
+    coefficients as it goes; afterwards the mixed-precision mass solve at 32
+    columns (the grouped kernel with whatever group size won) still equals the
+    per-row FP32 passes bit for bit (and the FP64 solve within the passes'
+    error bound, (2 r^12)^2 = 3.2e-5 in the M-norm)."""
+    import torch
+    import paper_1906_11082_amd as nm
+    d = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    monkeypatch.setenv("NM_ROW_GROUPS", "0")
+    P0 = nm.Pencil(d)
+    rng = np.random.default_rng(3)
+    F = torch.from_numpy(rng.standard_normal((P0.n, 32))).cuda()
+    Y_row = P0.apply(nm.OP_MINV, F, kM=12, mass_passes=2).cpu().numpy()
+    monkeypatch.delenv("NM_ROW_GROUPS")
+    G = nm.Pencil(d)
+    Y64 = G.apply(nm.OP_MINV, F, kM=40).cpu().numpy()
+    monkeypatch.setenv("NM_AUTOTUNE_VERBOSE", "1")
+    blk, us = G.autotune(1)
+    err = capfd.readouterr().err
+    print(err, flush=True)
+    assert "kernel=group tile_rows=0 group_rows=4" in err and "kernel=group tile_rows=0 group_rows=8" in err
+    Y = G.apply(nm.OP_MINV, F, kM=12, mass_passes=2).cpu().numpy()
+    assert np.array_equal(Y, Y_row)
+    assert np.abs(Y - Y64).max() <= 1e-3 * np.abs(Y64).max()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replayed_filter_equals_eager(monkeypatch, precision):
     """Small problems capture one filter application in a HIP graph and replay
