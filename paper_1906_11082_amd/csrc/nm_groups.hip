@@ -146,6 +146,7 @@ void build_row_groups(nm_pencil* P, hipStream_t st, int rows) {
   // the union list is padded by 4 entries: the grouped kernel stages it in
   // 16-byte pieces from a 4-entry boundary
   DBuf<int32_t> gptr(ng + 1), gcol((size_t)ptr[ng] + 4);
+  NM_HIP(hipMemsetAsync(gcol.p + ptr[ng], 0, 4 * sizeof(int32_t), st));
   DBuf<uint16_t> lcol(std::max<int64_t>(P->nnzb, 1));
   NM_HIP(hipMemcpyAsync(gptr.p, ptr.data(), 4 * (ng + 1), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_group_union, dim3((unsigned)ng), dim3(256), 0, st, N, R, P->row_ptr.p, P->col.p, 1, nullptr,
