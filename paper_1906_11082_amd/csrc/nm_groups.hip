@@ -118,6 +118,9 @@ void build_row_groups(nm_pencil* P, hipStream_t st, int rows) {
     // NM_ROW_GROUPS: 0 per-row kernel only, 1 (default) grouped from 32 columns, 2 grouped at any width
     const char* env = getenv("NM_ROW_GROUPS");
     P->grouped = env ? atoi(env) : 1;
+    // NM_PERSIST=1: each grouped step as one persistent launch
+    const char* penv = getenv("NM_PERSIST");
+    P->persist = penv ? atoi(penv) : 0;
     if (P->grouped <= 0) {
       P->grouped = 0;
       return;

@@ -153,6 +153,7 @@ struct nm_pencil {
   nm::DBuf<double> grp_coef;
   nm::DBuf<float> grp_coef32;  // FP32 shadow (built with the other FP32 shadows)
   int grouped = 1;  // 0: per-row kernels only; 1: grouped from 32 columns; 2: grouped at any width
+  int persist = 0;  // 1: each row-group step as one persistent launch (k_cj_group_persist)
   // LDS tiles of the node graph (tiled mass solve): tile_rows consecutive internal rows, the
   // sorted union of their columns, and each nonzero's position in its tile's union;
   // tile_umax / tile_emax: largest union and largest entry count of a tile (0: no tiles)

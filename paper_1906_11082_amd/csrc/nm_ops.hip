@@ -18,9 +18,13 @@
 // With mass passes (ApplyCfg::mixP) the M solve of an FP64 filter runs as
 // FP32 passes of the same iteration joined by FP64 residual corrections
 // (mass_solve_mixed); the update is then fused into the final FP64 sum.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "nm_internal.h"
 
@@ -484,13 +488,18 @@ __device__ __forceinline__ void group_sum(const int32_t* cl, const T* cf, int32_
 // bound the step through the texture-address unit) drops by the ratio of
 // the rows' entries to the size of their union.  Union columns and
 // coefficients of the workgroup's groups are staged in LDS.
-template <class T, int V, int R, int U = 4, int GC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cj_group(
-    uint32_t N, uint32_t w, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
-    const T* __restrict__ gcoef, const T* __restrict__ dinv, const T* __restrict__ f, const T* __restrict__ ycur,
-    const T* yprev, T alpha, T beta, int prev_zero, int mode, T* out, const T* __restrict__ win, const T* wprev, T a1,
-    T cs, T a2, int ymode, T mu0, T mu, const T* __restrict__ mu0c, const T* __restrict__ muc, T* wout,
-    T* Yacc) {
+#define NM_CJ_GROUP_PARAMS                                                                                       \
+  uint32_t N, uint32_t w, const int32_t *__restrict__ gptr, const int32_t *__restrict__ gcol,                      \
+      const T *__restrict__ gcoef, const T *__restrict__ dinv, const T *__restrict__ f,                            \
+      const T *__restrict__ ycur, const T *yprev, T alpha, T beta, int prev_zero, int mode, T *out,                \
+      const T *__restrict__ win, const T *wprev, T a1, T cs, T a2, int ymode, T mu0, T mu,                         \
+      const T *__restrict__ mu0c, const T *__restrict__ muc, T *wout, T *Yacc
+#define NM_CJ_GROUP_ARGS                                                                                         \
+  N, w, gptr, gcol, gcoef, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, \
+      mu0, mu, mu0c, muc, wout, Yacc
+// one workgroup's share: the groups whose lanes fall in [vblock * 256, vblock * 256 + 256)
+template <class T, int V, int R, int U, int GC>
+__device__ __forceinline__ void cj_group_block(uint32_t vblock, NM_CJ_GROUP_PARAMS) {
   // LDS stage: 640 union entries in FP64 (23 KB), 896 in FP32 (18 KB, so 8
   // workgroups fit a CU; measured 3 % faster than 1280 at C2, 32 columns).
   // The waves-per-SIMD hint asks for at most 64 VGPRs, which the FP32 4-row
@@ -502,8 +511,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   __shared__ __align__(16) T s_cf[GCAP * R];
   const uint32_t wl = w / V;
   const uint32_t ngroups = (N + R - 1) / R;
-  const uint32_t g = lane_id();
-  const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
+  const uint32_t g0 = vblock * blockDim.x;
+  const uint32_t g = g0 + threadIdx.x;
   const uint32_t G0 = min(g0 / wl, ngroups - 1), G1 = min((g0 + blockDim.x - 1) / wl, ngroups - 1);
   const int32_t lb = gptr[G0], le = gptr[G1 + 1];
   // columns staged from lb rounded down to 4 entries (the union list is
@@ -581,6 +590,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     }
   }
 }
+
+
+// one launch per step: workgroup i takes the i-th share of the XCD-aware order
+template <class T, int V, int R, int U = 4, int GC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cj_group(NM_CJ_GROUP_PARAMS) {
+  cj_group_block<T, V, R, U, GC>((uint32_t)nm_xcd_block(), NM_CJ_GROUP_ARGS);
+}
+
+// persistent form: as many workgroups as the GPU holds at once (a multiple
+// of 8); the workgroups of XCD x sweep that XCD's contiguous eighth of the
+// nvb shares in order, so the L2 of each XCD sees the same rows as in the
+// one-share-per-workgroup launch, and every workgroup leaves its loop after
+// at most ceil(nvb / gridDim.x) + 1 shares
+template <class T, int V, int R, int U = 4, int GC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cj_group_persist(
+    uint32_t nvb, NM_CJ_GROUP_PARAMS) {
+  const uint32_t x = blockIdx.x & 7u, per = gridDim.x >> 3, k = blockIdx.x >> 3;
+  const uint32_t span = (nvb + 7u) / 8u, lo = x * span, hi = min(nvb, lo + span);
+  for (uint32_t vb = lo + k; vb < hi; vb += per) {
+    cj_group_block<T, V, R, U, GC>(vb, NM_CJ_GROUP_ARGS);
+    __syncthreads();  // the next share restages the LDS
+  }
+}
+#undef NM_CJ_GROUP_PARAMS
+#undef NM_CJ_GROUP_ARGS
 
 // LDS-tiled Chebyshev-Jacobi step (same arithmetic, modes and summation
 // order as k_cj_step, so the results are bit-identical).  A workgroup owns
@@ -942,6 +976,7 @@ void launch_cj_first(int64_t rows, int w, const T* dinv, const T* f, T inv_theta
 // row-group launch plan for the mass solve (displacement rows)
 struct GroupPlan {
   bool on = false;
+  bool persist = false;  // one persistent launch per step (k_cj_group_persist)
   int R = 0;
   const int32_t *gptr = nullptr, *gcol = nullptr;
   const void* gcoef = nullptr;
@@ -959,6 +994,7 @@ GroupPlan group_plan(const nm_pencil* P, int b) {
   const void* cf = sizeof(T) == 8 ? (const void*)P->grp_coef.p : (const void*)P->grp_coef32.p;
   if (!cf) return tp;
   tp.on = true;
+  tp.persist = P->persist > 0;
   tp.R = P->grp_rows;
   tp.gptr = P->grp_ptr.p;
   tp.gcol = P->grp_col.p;
@@ -1028,17 +1064,48 @@ void launch_cj_tile(const nm_pencil* P, const TilePlan& tp, const T* val, int64_
 #undef NM_TILE
 }
 
+// workgroups of a persistent launch: the device's CUs times the workgroups
+// of this kernel one CU holds, rounded down to a multiple of 8 (queried once
+// per kernel and device)
+template <class K>
+unsigned persistent_grid(K kernel) {
+  static std::mutex mx;
+  static std::map<std::pair<const void*, int>, unsigned> cache;
+  int dev = 0;
+  NM_HIP(hipGetDevice(&dev));
+  const std::pair<const void*, int> key((const void*)kernel, dev);
+  std::lock_guard<std::mutex> lk(mx);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  NM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+  NM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const unsigned g = std::max(8u, (unsigned)(std::max(per_cu, 1) * std::max(cus, 1)) / 8u * 8u);
+  cache[key] = g;
+  return g;
+}
+
 template <class T>
 void launch_cj_group(const GroupPlan& tp, int64_t N, int w, const T* dinv, const T* f, const T* ycur, const T* yprev,
                      T alpha, T beta, int prev_zero, int mode, T* out, const T* win, const T* wprev, T a1, T cs, T a2,
                      int ymode, T mu0, T mu, const T* mu0c, const T* muc, T* wout, T* Yacc, hipStream_t st) {
   const int v = pick_v<T>(w);
   const int64_t lanes = (N + tp.R - 1) / tp.R * (w / v);
+  const uint32_t nvb = (uint32_t)((lanes + 255) / 256);
   const T* cf = (const T*)tp.gcoef;
-#define NM_GRP(VV, RR)                                                                                              \
-  hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,     \
-                     tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev, a1,  \
-                     cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc)
+#define NM_GRP(VV, RR)                                                                                               \
+  do {                                                                                                               \
+    if (tp.persist) {                                                                                                \
+      const unsigned pg = persistent_grid(k_cj_group_persist<T, VV, RR>);                                            \
+      hipLaunchKernelGGL((k_cj_group_persist<T, VV, RR>), dim3(std::min(pg, (nvb + 7u) / 8u * 8u)), dim3(256), 0, st, \
+                         nvb, (uint32_t)N, (uint32_t)w, tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta,     \
+                         prev_zero, mode, out, win, wprev, a1, cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc);        \
+    } else {                                                                                                         \
+      hipLaunchKernelGGL((k_cj_group<T, VV, RR>), dim3(grid_for(lanes)), dim3(256), 0, st, (uint32_t)N, (uint32_t)w,  \
+                         tp.gptr, tp.gcol, cf, dinv, f, ycur, yprev, alpha, beta, prev_zero, mode, out, win, wprev,  \
+                         a1, cs, a2, ymode, mu0, mu, mu0c, muc, wout, Yacc);                                         \
+    }                                                                                                                \
+  } while (0)
   if (tp.R == 8) {
     if (v == 4) NM_GRP(4, 8); else if (v == 2) NM_GRP(2, 8); else NM_GRP(1, 8);
   } else {
@@ -1528,18 +1595,19 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
   NM_HIP(hipEventCreate(&e1));
   double best = 1e300;
   const int rows0 = P->grp_rows;
-  int bb = 16, bgrp = P->grouped, btile = 0, brows = rows0;
+  int bb = 16, bgrp = P->grouped, btile = 0, brows = rows0, bpersist = P->persist;
   // candidate kernels: (tile rows, grouped mode, rows per group); tile rows 0
   // = no tiles.  The row-group size is the block size of the grouped format
   // (rows x their column union, zero-padded): larger groups gather fewer
   // neighbour rows per output row but carry more coefficients and registers.
   struct Cand {
-    int tr, grouped, rows;
+    int tr, grouped, rows, persist;
   };
-  std::vector<Cand> cands = {{0, 0, 0}};
+  std::vector<Cand> cands = {{0, 0, 0, 0}};
   if (rows0 > 0)
-    for (int r : {4, 8}) cands.push_back({0, 2, r});
-  for (int tr : {32, 64}) cands.push_back({tr, 0, 0});
+    for (int r : {4, 8})
+      for (int pe : {0, 1}) cands.push_back({0, 2, r, pe});
+  for (int tr : {32, 64}) cands.push_back({tr, 0, 0, 0});
   const char* venv = getenv("NM_AUTOTUNE_VERBOSE");
   const bool verbose = venv && atoi(venv) != 0;
   for (const Cand& cd : cands) {
@@ -1554,6 +1622,7 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
       if (P->grp_rows != cd.rows) continue;  // a group of this size does not fit the union sort
     }
     P->grouped = cd.grouped;
+    P->persist = cd.persist;
     for (int b : {8, 16, 32, 64}) {
       const MassPlan<T> tp = mass_plan<T>(P, b);
       if (cd.tr > 0 && !tp.tile.on) continue;
@@ -1573,15 +1642,17 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
       const double us = 1e3 * ms / reps / b;
       if (verbose)
         fprintf(stderr,
-                "[autotune] %s b=%d kernel=%s tile_rows=%d group_rows=%d: %.1f us per step, %.3f us per column\n",
+                "[autotune] %s b=%d kernel=%s tile_rows=%d group_rows=%d persistent=%d: %.1f us per step, %.3f us "
+                "per column\n",
                 sizeof(T) == 8 ? "fp64" : "fp32", b, tp.tile.on ? "tile" : (tp.group.on ? "group" : "row"), cd.tr,
-                tp.group.on ? P->grp_rows : 0, 1e3 * ms / reps, us);
+                tp.group.on ? P->grp_rows : 0, tp.group.on && tp.group.persist ? 1 : 0, 1e3 * ms / reps, us);
       if (us < best) {
         best = us;
         bb = b;
         bgrp = cd.grouped;
         btile = cd.tr;
         brows = cd.rows > 0 ? cd.rows : rows0;
+        bpersist = cd.persist;
       }
     }
   }
@@ -1594,6 +1665,7 @@ static void autotune_t(nm_pencil* P, hipStream_t st, int* best_b, double* best_u
   }
   if (brows > 0 && P->grp_rows != brows) build_row_groups(P, st, brows);
   P->grouped = bgrp;
+  P->persist = bpersist;
   P->tuned_block = bb;
   P->tuned_tile = btile;
   *best_b = bb;

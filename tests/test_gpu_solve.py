@@ -238,10 +238,43 @@ def test_autotune_times_group_sizes_and_keeps_fp32_coefficients(capfd, monkeypat
     blk, us = G.autotune(1)
     err = capfd.readouterr().err
     print(err, flush=True)
-    assert "kernel=group tile_rows=0 group_rows=4" in err and "kernel=group tile_rows=0 group_rows=8" in err
+    for rows in (4, 8):
+        for pe in (0, 1):
+            assert "kernel=group tile_rows=0 group_rows=%d persistent=%d" % (rows, pe) in err
     Y = G.apply(nm.OP_MINV, F, kM=12, mass_passes=2).cpu().numpy()
     assert np.array_equal(Y, Y_row)
     assert np.abs(Y - Y64).max() <= 1e-3 * np.abs(Y64).max()
+
+
+def test_persistent_group_step_equals_one_launch_per_share(monkeypatch):
+    """The persistent form of the row-group step (as many workgroups as the
+    GPU holds, each sweeping its XCD's shares in order) computes every share
+    exactly as the one-workgroup-per-share launch: FP64 and mixed mass solves
+    at 32 and 64 columns on the 83k-tet planet (2,877 and 5,753 shares, more
+    than the persistent grid holds, so workgroups take several) and a whole
+    mixed-precision solve on a small planet are bit-identical."""
+    import torch
+    import paper_1906_11082_amd as nm
+    big = make_planet("three_layer_planet", n_half=12, order=2, pres_order=1)
+    small = make_planet("three_layer_planet", n_half=4, order=2, pres_order=1)
+    rng = np.random.default_rng(5)
+    out = {}
+    for persist in ("0", "1"):
+        monkeypatch.setenv("NM_PERSIST", persist)
+        G = nm.Pencil(big)
+        for b in (32, 64):
+            if persist == "0":
+                out[("F", b)] = rng.standard_normal((G.n, b))
+            F = torch.from_numpy(out[("F", b)]).cuda()
+            out[(persist, b, "fp64")] = G.apply(nm.OP_MINV, F, kM=14).cpu().numpy()
+            out[(persist, b, "mixed")] = G.apply(nm.OP_MINV, F, kM=12, mass_passes=2).cpu().numpy()
+        del G
+        r = nm.Pencil(small).filtered_eig(1.0, 12.0, 200, 1e-9, block=32, mass_passes=2)
+        out[(persist, "lam")] = r.lam
+    for b in (32, 64):
+        for leg in ("fp64", "mixed"):
+            assert np.array_equal(out[("0", b, leg)], out[("1", b, leg)]), (b, leg)
+    assert np.array_equal(out[("0", "lam")], out[("1", "lam")])
 
 
 @pytest.mark.parametrize("precision", [0, 1])
