@@ -249,8 +249,9 @@ nm_status nm_pencil_apply_noalloc(const nm_pencil* p, int32_t op, int32_t ncols,
  * this pencil, in FP64 (precision 0) or FP32 (1): times middle
  * Chebyshev-Jacobi steps for block widths 8, 16, 32 and 64 with the per-row
  * kernel, the row-group kernel at groups of 4 and of 8 rows (the block size
- * of the grouped format: rows times the union of their columns), and the
- * LDS-tile kernel at tiles of 32 and 64 rows, then keeps the fastest per
+ * of the grouped format: rows times the union of their columns), each as one
+ * workgroup per share or as a persistent launch, and the LDS-tile kernel at
+ * tiles of 32 and 64 rows, then keeps the fastest per
  * column: nm_filtered_eig with block 0 uses that width (at most nev / 4,
  * rounded down to a multiple of 8, at least 8) and every later mass solve
  * that kernel and block size (the row groups and tiles are rebuilt for it).
