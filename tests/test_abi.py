@@ -185,3 +185,15 @@ def test_block_products_reject_bad_arguments(lib):
     assert lib.nm_gemm_nn(10, 8, 4, 1.0, dummy, 8, dummy, 8, 0.0, None, 4, None) == -1   # null D
     assert lib.nm_gemm_nn(10, 8, 4, 1.0, dummy, 8, C.c_void_p(512), 8, 0.0, dummy, 4, None) == -1  # A == D
     assert "gemm" in lib.nm_last_error().decode() or "null" in lib.nm_last_error().decode()
+
+
+def test_block_product_wrappers_check_their_tensors():
+    """The Python wrappers of the block products accept only 2-D float64
+    device tensors with contiguous rows and matching row counts (checked
+    before any library call, so this runs without a GPU)."""
+    import torch
+    import paper_1906_11082_amd as nm
+    with pytest.raises(ValueError):
+        nm.gemm_tn(torch.zeros((4, 3), dtype=torch.float64), torch.zeros((4, 2), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        nm.gemm_nn(torch.zeros((4, 3), dtype=torch.float32), torch.zeros((3, 2)))
