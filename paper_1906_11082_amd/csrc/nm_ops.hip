@@ -509,12 +509,14 @@ __device__ __forceinline__ void cj_group_block(uint32_t vblock, NM_CJ_GROUP_PARA
   static_assert(GCAP % 4 == 0 && (R * sizeof(T)) % 16 == 0, "16-byte LDS staging");
   __shared__ __align__(16) int32_t s_col[GCAP];
   __shared__ __align__(16) T s_cf[GCAP * R];
+  __shared__ int32_t s_gp[256 + 2];  // union bounds of the workgroup's groups (at most 256 + 1 of them)
   const uint32_t wl = w / V;
   const uint32_t ngroups = (N + R - 1) / R;
   const uint32_t g0 = vblock * blockDim.x;
   const uint32_t g = g0 + threadIdx.x;
   const uint32_t G0 = min(g0 / wl, ngroups - 1), G1 = min((g0 + blockDim.x - 1) / wl, ngroups - 1);
   const int32_t lb = gptr[G0], le = gptr[G1 + 1];
+  for (uint32_t i = threadIdx.x; i < G1 - G0 + 2; i += blockDim.x) s_gp[i] = gptr[G0 + i];
   // columns staged from lb rounded down to 4 entries (the union list is
   // padded by 4 entries at its end), coefficients from lb: both copied in
   // 16-byte pieces
@@ -537,11 +539,20 @@ __device__ __forceinline__ void cj_group_block(uint32_t vblock, NM_CJ_GROUP_PARA
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int i = 0; i < V; ++i) acc[r].v[i] = T(0);
-  const int32_t l0 = gptr[grp], l1 = gptr[grp + 1];
+  const int32_t l0 = s_gp[grp - G0], l1 = s_gp[grp - G0 + 1];
   if (staged)
     group_sum<T, V, R, U>(s_col, s_cf, cb, lb, l0, l1, ycur, w, e, acc);
   else
     group_sum<T, V, R, U>(gcol, gcoef, 0, 0, l0, l1, ycur, w, e, acc);
+  // the group's R diagonal entries in one piece (all R rows exist except in the last group)
+  T dv[R];
+  if (r0 + R <= N) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) dv[r] = dinv[r0 + r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) dv[r] = r0 + r < N ? dinv[r0 + r] : T(0);
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t row = r0 + r;
@@ -556,7 +567,7 @@ __device__ __forceinline__ void cj_group_block(uint32_t vblock, NM_CJ_GROUP_PARA
     } else {
       yp = ldv_nt<T, V>(yprev + o);
     }
-    const T bd = beta * dinv[row];
+    const T bd = beta * dv[r];
     Vx<T, V> z;
 #pragma unroll
     for (int i = 0; i < V; ++i) z.v[i] = yc.v[i] + alpha * (yc.v[i] - yp.v[i]) + bd * (ff.v[i] - acc[r].v[i]);
