@@ -519,16 +519,20 @@ __device__ __forceinline__ void cj_group_block(uint32_t vblock, NM_CJ_GROUP_PARA
   for (uint32_t i = threadIdx.x; i < G1 - G0 + 2; i += blockDim.x) s_gp[i] = gptr[G0 + i];
   // columns staged from lb rounded down to 4 entries (the union list is
   // padded by 4 entries at its end), coefficients from lb: both copied in
-  // 16-byte pieces
+  // 16-byte pieces, with nontemporal loads (each entry is read by one
+  // workgroup once per step, so it should not displace gathered rows from L2)
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
   const int32_t cb = lb & ~3;
   const bool staged = le - cb <= GCAP;
   if (staged) {
     const int32_t nc = (le - cb + 3) >> 2;
-    const int4* sc = reinterpret_cast<const int4*>(gcol + cb);
-    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) reinterpret_cast<int4*>(s_col)[i] = sc[i];
+    const i32x4* sc = reinterpret_cast<const i32x4*>(gcol + cb);
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x)
+      reinterpret_cast<i32x4*>(s_col)[i] = __builtin_nontemporal_load(sc + i);
     const int32_t nq = (int32_t)((size_t)(le - lb) * R * sizeof(T) / 16);
-    const int4* sf = reinterpret_cast<const int4*>(gcoef + (size_t)lb * R);
-    for (int32_t i = threadIdx.x; i < nq; i += blockDim.x) reinterpret_cast<int4*>(s_cf)[i] = sf[i];
+    const i32x4* sf = reinterpret_cast<const i32x4*>(gcoef + (size_t)lb * R);
+    for (int32_t i = threadIdx.x; i < nq; i += blockDim.x)
+      reinterpret_cast<i32x4*>(s_cf)[i] = __builtin_nontemporal_load(sf + i);
   }
   __syncthreads();
   if (g >= ngroups * wl) return;
