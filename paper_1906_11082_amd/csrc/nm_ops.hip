@@ -217,19 +217,35 @@ __global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const 
                                                   const T* __restrict__ S, T* __restrict__ F,
                                                   const T* __restrict__ dinv, T inv_theta, T* __restrict__ Y1) {
   constexpr int CAP = STAGE_CAP / 4;
-  __shared__ int32_t s_col[CAP];
-  __shared__ T s_val[9 * CAP];
+  constexpr int PV = 16 / sizeof(T);  // values per 16-byte piece
+  __shared__ __align__(16) int32_t s_col[CAP + 4];
+  __shared__ __align__(16) T s_val[9 * CAP + PV];
   const uint32_t w = 3 * b, bl = b / V;
   const uint32_t g = lane_id();
   const bool active = g < N * bl;
-  // stage (indices and 3x3 blocks) of this workgroup's rows
+  // stage (indices and 3x3 blocks) of this workgroup's rows: whole 16-byte
+  // pieces from the 16-byte boundary at or below the first entry, with
+  // nontemporal loads (each block is read once per product, so it should not
+  // displace gathered rows from L2), and the few entries past the last whole
+  // piece one by one
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
   const uint32_t g0 = (uint32_t)nm_xcd_block() * blockDim.x;
   const uint32_t r0 = min(g0 / bl, N - 1), r1 = min((g0 + blockDim.x - 1) / bl, N - 1);
   const int32_t kb = rp[r0], ke = rp[r1 + 1];
   const bool staged = ke - kb <= CAP;
+  const int32_t cb = kb & ~3;
+  const int64_t vb = (9 * (int64_t)kb) & ~(int64_t)(PV - 1), ve = 9 * (int64_t)ke;
   if (staged) {
-    for (int32_t i = threadIdx.x; i < ke - kb; i += blockDim.x) s_col[i] = col[kb + i];
-    for (int32_t i = threadIdx.x; i < 9 * (ke - kb); i += blockDim.x) s_val[i] = ag[9 * (size_t)kb + i];
+    const int32_t nc = (ke - cb) >> 2;
+    const i32x4* sc = reinterpret_cast<const i32x4*>(col + cb);
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x)
+      reinterpret_cast<i32x4*>(s_col)[i] = __builtin_nontemporal_load(sc + i);
+    for (int32_t i = cb + 4 * nc + threadIdx.x; i < ke; i += blockDim.x) s_col[i - cb] = col[i];
+    const int32_t nv = (int32_t)((ve - vb) / PV);
+    const i32x4* sv = reinterpret_cast<const i32x4*>(ag + vb);
+    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x)
+      reinterpret_cast<i32x4*>(s_val)[i] = __builtin_nontemporal_load(sv + i);
+    for (int64_t i = vb + (int64_t)PV * nv + threadIdx.x; i < ve; i += blockDim.x) s_val[i - vb] = ag[i];
   }
   __syncthreads();
   if (!active) return;
@@ -238,7 +254,7 @@ __global__ __launch_bounds__(256) void k_apply_ag(uint32_t N, uint32_t b, const 
   const int32_t k0 = rp[row], k1 = rp[row + 1];
   Vx<T, V> acc[3];
   if (staged)
-    ag_row<T, V>(s_col, s_val, kb, k0, k1, X, w, b, v, acc);
+    ag_row<T, V>(s_col + (kb - cb), s_val + (9 * (int64_t)kb - vb), kb, k0, k1, X, w, b, v, acc);
   else
     ag_row<T, V>(col, ag, 0, k0, k1, X, w, b, v, acc);
   if (S) {
